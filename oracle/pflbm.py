@@ -1,0 +1,294 @@
+"""FP64 CPU oracle of one coupled phase-field LBM time step.
+
+Test infrastructure only (see oracle/__init__.py).  Plain PyTorch CPU ops in
+float64, vectorised over cells but otherwise taking the steps of the method
+in the order below, with two-buffer (A -> B) streaming and dense
+M^-1 S M collision matrices.  Nothing here is shared with the HIP library.
+
+State: h [15, N] (phase field, D3Q15) and g [27, N] (hydrodynamics, D3Q27),
+post-streaming, with N = nx*ny*nz cells and cell index x + nx*(y + ny*z).
+Solid cells hold zeros and are never updated.
+
+One step n -> n+1 (paper sec. "Conservative Allen-Cahn model"):
+  S1  phi_c = sum_i h_i                               (eq. zeroth_moment_phase)
+  S2  neighbour phi over D3Q27, periodic wrap; a solid or out-of-box
+      neighbour takes the cell's own phi (no-flux wall, 90 degree contact)
+  S3  grad phi = 3 sum_k w_k c_k (phi_k - phi) ; lap phi = 6 sum_k w_k (phi_k - phi)
+      (the gradient is written with the cell's own value subtracted, which is
+      the same stencil since sum_k w_k c_k = 0, and is exactly zero on a
+      uniform field, so rounding cannot feed the normalised n below)
+  S4  n = grad phi / sqrt(|grad phi|^2 + eps^2) ; theta = 4 phi (1-phi) / xi
+  S5  rho(phi), tau(phi) by linear interpolation, omega = 1/tau
+  S6  mu_phi = 4 beta phi (phi-1)(phi-1/2) - kappa lap phi,
+      beta = 12 sigma/xi, kappa = 3 sigma xi / 2
+  S7  p* = sum_i g_i (eq. zeroth_moment_hydro), j = sum_i c_i g_i
+  S8  F_s = mu_phi grad phi, F_b = rho g, F_p = -p* c_s^2 (rho_H - rho_L) grad phi
+  S9  u' = j + (F_s + F_b + F_p) / (2 rho)
+  S10 Pi_neq = sum_i c_i c_i^T (g_i - g_i^eq(p*, u')),
+      F_mu = -(1 - omega/2)(rho_H - rho_L) Pi_neq grad phi
+      (the viscous force from non-equilibrium moments instead of finite
+      differences of u, as the paper remarks at the end of the LBE section)
+  S11 F = F_s + F_b + F_p + F_mu ; u = j + F / (2 rho)
+  S12 g^eq_i = w_i [p* + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u]  (eq. feq, rho_0 = 1)
+      F^g_i = 3 w_i c_i.F / rho
+  S13 g*_i = g_i + [M^-1 S M (g^eq - g)]_i + [M^-1 (I - S/2) M F^g]_i
+  S14 h^eq_i = phi w_i [1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u] ; F^h_i = w_i theta c_i.n
+  S15 h*_i = h_i + [M^-1 S M (h^eq - h)]_i + [M^-1 (I - S/2) M F^h]_i
+  S16 streaming (eq. streaming): f_i(x + c_i) = f*_i(x); if x + c_i is solid
+      or outside a wall, f_opp(i)(x) = f*_i(x) (halfway bounce-back)
+  S17 phi^{n+1} = sum_i h_i^{n+1}
+
+Relaxation rates (one rate per polynomial degree of the moment basis):
+  h: degrees 1 and 2 relax with omega_phi = 1/(3M + 1/2) (tau_phi = M/c_s^2 is
+     the relaxation time measured from the half-step, eq. pflbm-tau), degrees
+     >= 3 with s_high.
+  g: degrees <= 2 relax with omega(phi), degrees >= 3 with s_high.
+  BGK: every degree relaxes with omega_phi (h) or omega(phi) (g) (eq. BGK).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Union
+
+import numpy as np
+import torch
+
+from .lattice import CS2, D3Q15, D3Q27, Lattice
+
+Num = Union[float, torch.Tensor]
+EPS_NORMAL = 1e-12
+F64 = torch.float64
+
+
+@dataclasses.dataclass
+class OracleParams:
+    tau_H: float
+    tau_L: float
+    mobility: Num
+    xi: float
+    sigma: Num
+    rho_H: float
+    rho_L: float
+    g: tuple
+    s_high: float = 1.0
+    collision: str = "mrt"  # "mrt" or "bgk"
+
+    @classmethod
+    def from_workload(cls, p, collision="mrt") -> "OracleParams":
+        return cls(p.tau_H, p.tau_L, p.mobility, p.xi, p.sigma, p.rho_H, p.rho_L,
+                   tuple(p.g), p.s_high, collision)
+
+
+class Grid:
+    """Box of nx*ny*nz cells with per-axis periodicity and an optional solid mask."""
+
+    def __init__(self, nx: int, ny: int, nz: int, periodic=(True, True, True),
+                 solid: Optional[np.ndarray] = None):
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.N = nx * ny * nz
+        self.periodic = tuple(bool(p) for p in periodic)
+        if solid is None:
+            self.solid = torch.zeros(self.N, dtype=torch.bool)
+        else:
+            self.solid = torch.as_tensor(np.asarray(solid, dtype=bool).reshape(-1))
+        self.fluid = ~self.solid
+        z, y, x = torch.meshgrid(torch.arange(nz), torch.arange(ny), torch.arange(nx),
+                                 indexing="ij")
+        self._xyz = (x.reshape(-1), y.reshape(-1), z.reshape(-1))
+        self._cache = {}
+
+    def neighbour(self, c):
+        """(index of x + c, valid) for every cell x; valid = inside the box and fluid."""
+        key = tuple(int(v) for v in c)
+        if key not in self._cache:
+            inside = torch.ones(self.N, dtype=torch.bool)
+            coords = []
+            for ax, (v, n) in enumerate(zip(self._xyz, (self.nx, self.ny, self.nz))):
+                t = v + key[ax]
+                if self.periodic[ax]:
+                    t = torch.remainder(t, n)
+                else:
+                    inside &= (t >= 0) & (t < n)
+                    t = t.clamp(0, n - 1)
+                coords.append(t)
+            idx = coords[0] + self.nx * (coords[1] + self.ny * coords[2])
+            valid = inside & self.fluid[idx]
+            self._cache[key] = (idx, valid)
+        return self._cache[key]
+
+
+def _as_t(v) -> torch.Tensor:
+    return v if isinstance(v, torch.Tensor) else torch.tensor(float(v), dtype=F64)
+
+
+def equilibrium(lat: Lattice, zeroth: torch.Tensor, u: torch.Tensor, scale_by_zeroth: bool):
+    """Paper eq. feq with rho_0 = 1 (incompressible form).
+
+    g form (scale_by_zeroth=False): w_i [p* + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u]
+    h form (scale_by_zeroth=True):  phi w_i [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u]
+    """
+    cu = lat.c @ u                       # [q, N]
+    uu = (u * u).sum(0)                  # [N]
+    poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu
+    w = lat.w[:, None]
+    if scale_by_zeroth:
+        return w * zeroth * (1.0 + poly)
+    return w * (zeroth + poly)
+
+
+def mrt_apply(lat: Lattice, rates: torch.Tensor, vec: torch.Tensor) -> torch.Tensor:
+    """M^-1 diag(rates) M vec, per cell (rates [q, N] or [q, 1])."""
+    return lat.Minv @ (rates * (lat.M @ vec))
+
+
+def _rates(lat: Lattice, low: torch.Tensor, s_high, bgk: bool, n: int) -> torch.Tensor:
+    """Per-moment, per-cell rate: degree <= 2 -> low, degree >= 3 -> s_high (or low if BGK)."""
+    low = low.reshape(1, -1).expand(lat.q, n) if low.dim() > 0 else low.reshape(1, 1).expand(lat.q, n)
+    hi = low if bgk else torch.full_like(low, float(s_high))
+    return torch.where((lat.degree >= 3)[:, None], hi, low)
+
+
+def collide(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
+    """S1-S15.  Returns (h*, g*, aux) where aux holds the cell moments and forces."""
+    LH, LG = D3Q15, D3Q27
+    N = grid.N
+    bgk = prm.collision == "bgk"
+    drho = prm.rho_H - prm.rho_L
+    # S1 (the phi field of S2 is the same quantity, phi^n = sum_i h_i^n)
+    phi = h.sum(0)
+    # S2, S3
+    grad = torch.zeros(3, N, dtype=F64)
+    lap = torch.zeros(N, dtype=F64)
+    for k in range(LG.q):
+        ck = LG.c_np[k]
+        idx, valid = grid.neighbour(ck)
+        phik = torch.where(valid, phi[idx], phi)
+        grad = grad + 3.0 * LG.w[k] * LG.c[k][:, None] * (phik - phi)[None, :]
+        lap = lap + 6.0 * LG.w[k] * (phik - phi)
+    # S4
+    normal = grad / torch.sqrt((grad * grad).sum(0) + EPS_NORMAL ** 2)
+    if math.isinf(prm.xi):
+        theta = torch.zeros(N, dtype=F64)
+    else:
+        theta = 4.0 * phi * (1.0 - phi) / prm.xi
+    # S5
+    rho = prm.rho_L + phi * drho
+    tau = prm.tau_L + phi * (prm.tau_H - prm.tau_L)
+    omega = 1.0 / tau
+    # S6
+    sigma = _as_t(prm.sigma)
+    if math.isinf(prm.xi):
+        mu = torch.zeros(N, dtype=F64)
+    else:
+        beta = 12.0 * sigma / prm.xi
+        kappa = 1.5 * sigma * prm.xi
+        mu = 4.0 * beta * phi * (phi - 1.0) * (phi - 0.5) - kappa * lap
+    # S7
+    pstar = g.sum(0)
+    j = LG.c.t() @ g                      # [3, N]
+    # S8
+    Fs = mu[None, :] * grad
+    gvec = torch.tensor(prm.g, dtype=F64)[:, None]
+    Fb = rho[None, :] * gvec
+    Fp = -(pstar * CS2 * drho)[None, :] * grad
+    # S9
+    u1 = j + (Fs + Fb + Fp) / (2.0 * rho[None, :])
+    # S10
+    geq1 = equilibrium(LG, pstar, u1, False)
+    neq = g - geq1
+    Pi = torch.einsum("ia,ib,in->abn", LG.c, LG.c, neq)
+    Fmu = -((1.0 - 0.5 * omega) * drho)[None, :] * torch.einsum("abn,bn->an", Pi, grad)
+    # S11
+    F = Fs + Fb + Fp + Fmu
+    u = j + F / (2.0 * rho[None, :])
+    # S12, S13
+    geq = equilibrium(LG, pstar, u, False)
+    Fg = 3.0 * LG.w[:, None] * (LG.c @ F) / rho[None, :]
+    sg = _rates(LG, omega, prm.s_high, bgk, N)
+    gstar = g + mrt_apply(LG, sg, geq - g) + mrt_apply(LG, 1.0 - 0.5 * sg, Fg)
+    # S14, S15
+    heq = equilibrium(LH, phi, u, True)
+    Fh = LH.w[:, None] * theta[None, :] * (LH.c @ normal)
+    omega_phi = 1.0 / (3.0 * _as_t(prm.mobility) + 0.5)
+    sh = _rates(LH, omega_phi, prm.s_high, bgk, N)
+    hstar = h + mrt_apply(LH, sh, heq - h) + mrt_apply(LH, 1.0 - 0.5 * sh, Fh)
+    fl = grid.fluid[None, :]
+    hstar = torch.where(fl, hstar, torch.zeros_like(hstar))
+    gstar = torch.where(fl, gstar, torch.zeros_like(gstar))
+    aux = dict(phi=phi, u=u, pstar=pstar, rho=rho, F=F, grad=grad, lap=lap, mu=mu)
+    return hstar, gstar, aux
+
+
+def stream(grid: Grid, lat: Lattice, fstar: torch.Tensor) -> torch.Tensor:
+    """S16 in pull form: f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) if x - c_i is a wall/solid."""
+    rows = []
+    for i in range(lat.q):
+        idx, valid = grid.neighbour(-lat.c_np[i])
+        rows.append(torch.where(valid, fstar[i][idx], fstar[lat.opp[i]]))
+    out = torch.stack(rows)
+    return torch.where(grid.fluid[None, :], out, torch.zeros_like(out))
+
+
+def step(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
+    hs, gs, _ = collide(grid, prm, h, g)
+    return stream(grid, D3Q15, hs), stream(grid, D3Q27, gs)
+
+
+def run(grid: Grid, prm: OracleParams, h, g, nsteps: int):
+    for _ in range(nsteps):
+        h, g = step(grid, prm, h, g)
+    return h, g
+
+
+def init_equilibrium(grid: Grid, phi0, u0, pstar0):
+    """h = phi0 w_i [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u], g = g^eq(p*0, u0); zero in solids.
+
+    phi0 [N] or [nz,ny,nx]; u0 [3, ...]; pstar0 like phi0 (numpy or torch).
+    """
+    phi0 = torch.as_tensor(phi0, dtype=F64).reshape(-1)
+    u0 = torch.as_tensor(u0, dtype=F64).reshape(3, -1)
+    pstar0 = torch.as_tensor(pstar0, dtype=F64).reshape(-1)
+    h = equilibrium(D3Q15, phi0, u0, True)
+    g = equilibrium(D3Q27, pstar0, u0, False)
+    fl = grid.fluid[None, :]
+    return torch.where(fl, h, torch.zeros_like(h)), torch.where(fl, g, torch.zeros_like(g))
+
+
+def moments(grid: Grid, prm: OracleParams, h, g):
+    """(phi, u [3,N], p*) of the current state, with the force-corrected velocity."""
+    _, _, aux = collide(grid, prm, h, g)
+    fl = grid.fluid
+    z = torch.zeros((), dtype=F64)
+    return (torch.where(fl, aux["phi"], z), torch.where(fl[None], aux["u"], z),
+            torch.where(fl, aux["pstar"], z))
+
+
+def reductions(grid: Grid, h, g):
+    """[sum phi, sum p*, sum j_x, sum j_y, sum j_z] over fluid cells (fp64)."""
+    fl = grid.fluid
+    phi = h.sum(0)[fl].sum()
+    ps = g.sum(0)[fl].sum()
+    j = (D3Q27.c.t() @ g)[:, fl].sum(1)
+    return torch.stack([phi, ps, j[0], j[1], j[2]])
+
+
+def amplitude(grid: Grid, h, depth: float, x0: int = 0):
+    """Interface elevation a = <sum_y phi(x0, y, z)>_z - depth (column sum of phi)."""
+    phi = h.sum(0).reshape(grid.nz, grid.ny, grid.nx)
+    return phi[:, :, x0].sum(1).mean() - depth
+
+
+def interface_crossing(phi_col: np.ndarray, near: float) -> float:
+    """Position y where phi = 1/2 by linear interpolation between cell centres,
+    choosing the crossing nearest to `near` (paper: elevation of the phi = 0.5
+    level, sec. gravity-wave setup)."""
+    phi_col = np.asarray(phi_col, dtype=np.float64)
+    best = None
+    for j in range(len(phi_col) - 1):
+        a, b = phi_col[j] - 0.5, phi_col[j + 1] - 0.5
+        if a == 0.0 or a * b < 0:
+            y = (j + 0.5) + a / (a - b)
+            if best is None or abs(y - near) < abs(best - near):
+                best = y
+    return float("nan") if best is None else best

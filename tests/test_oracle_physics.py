@@ -1,0 +1,168 @@
+"""Closed-form pins of the oracle's dynamics (diffusion, advection, walls and
+forces, flat interface, Laplace law, capillary wave)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.integrate import cumulative_trapezoid
+from scipy.optimize import curve_fit
+
+import workloads as W
+from oracle import analytic as A
+from oracle import pflbm as P
+
+
+def _run(grid, prm, phi0, u0, p0, n):
+    h, g = P.init_equilibrium(grid, phi0, u0, p0)
+    return P.run(grid, prm, h, g, n)
+
+
+def test_phase_field_diffuses_at_the_mobility():
+    """xi = inf switches the counter-term off and u stays 0: the h-LBE is pure
+    diffusion with coefficient M, so a Fourier mode decays as exp(-M k^2 t).
+    Pins omega_phi = 1/(3M + 1/2) (paper eq. pflbm-tau)."""
+    nx, M, n = 64, 0.05, 400
+    grid = P.Grid(nx, 1, 1, (True, True, True))
+    x = np.arange(nx) + 0.5
+    k = 2 * math.pi / nx
+    prm = P.OracleParams(0.8, 0.8, M, math.inf, 0.0, 1.0, 1.0, (0, 0, 0))
+    h, _ = _run(grid, prm, 0.5 + 1e-3 * np.sin(k * x), np.zeros((3, nx)), np.zeros(nx), n)
+    amp = 2 * np.sum((h.sum(0).numpy() - 0.5) * np.sin(k * x)) / nx
+    rate = -math.log(amp / 1e-3) / n
+    assert abs(rate / (M * k * k) - 1) < 0.01
+
+
+def test_interface_advected_by_uniform_flow():
+    """Uniform u, no forces: the phase field translates by u t (pins the c.u
+    term of the phase-field equilibrium)."""
+    nx, U, n = 64, 0.02, 800
+    grid = P.Grid(nx, 1, 1, (True, True, True))
+    x = np.arange(nx) + 0.5
+    phi0 = 0.5 + 0.5 * np.tanh(2 * np.minimum(x - 16, 48 - x) / 4)
+    u0 = np.zeros((3, nx))
+    u0[0] = U
+    prm = P.OracleParams(0.8, 0.8, 0.02, 4.0, 0.0, 1.0, 1.0, (0, 0, 0))
+    h, _ = _run(grid, prm, phi0, u0, np.zeros(nx), n)
+
+    def centre(p):
+        return np.angle(np.sum(p * np.exp(2j * math.pi * x / nx))) * nx / (2 * math.pi)
+
+    shift = (centre(h.sum(0).numpy()) - centre(phi0)) % nx
+    assert abs(shift - U * n) < 1e-3
+
+
+def test_flat_interface_is_stationary_with_width_xi():
+    """A flat tanh interface at rest stays put, and the discrete equilibrium
+    profile keeps width xi.  Pins the counter-term factor 4 phi(1-phi)/xi and
+    its first moment c_s^2 theta n (a factor-3 error would sharpen it 3x)."""
+    ny, xi = 32, 4.0
+    grid = P.Grid(1, ny, 1, (True, False, True))
+    y = np.arange(ny) + 0.5
+    phi0 = 0.5 + 0.5 * np.tanh(2 * (16 - y) / xi)
+    prm = P.OracleParams(0.53, 0.53, 0.02, xi, 1e-4, 1.0, 1e-3, (0, 0, 0))
+    h, g = _run(grid, prm, phi0, np.zeros((3, ny)), np.zeros(ny), 2000)
+    phi = h.sum(0).numpy()
+    assert abs(P.interface_crossing(phi, 16.0) - 16.0) < 1e-4
+    (w, y0), _ = curve_fit(lambda yy, w, y0: 0.5 + 0.5 * np.tanh(2 * (y0 - yy) / w), y, phi,
+                           p0=(xi, 16.0))
+    assert abs(w / xi - 1) < 0.05
+    _, u, _ = P.moments(grid, prm, h, g)
+    assert torch.abs(u).max() < 1e-6
+
+
+def test_poiseuille_between_bounce_back_walls():
+    """Single phase, body force along x, walls at y = 0 and y = H (halfway
+    bounce-back): u(y) = g y (H - y) / (2 nu)."""
+    H, tau, ga = 16, 1.0, 1e-5
+    nu = (tau - 0.5) / 3
+    grid = P.Grid(1, H, 1, (True, False, True))
+    prm = P.OracleParams(tau, tau, 0.02, 4.0, 0.0, 1.0, 1.0, (ga, 0, 0))
+    h, g = _run(grid, prm, np.ones(H), np.zeros((3, H)), np.zeros(H), 2500)
+    _, u, _ = P.moments(grid, prm, h, g)
+    ref = A.poiseuille(np.arange(H) + 0.5, H, ga, nu)
+    assert np.abs(u[0].numpy() - ref).max() / ref.max() < 0.005
+
+
+def test_two_layer_channel_flow_matches_variable_viscosity_ode():
+    """Heavy layer below a light one (density ratio 10, equal nu), body force
+    rho g along x.  Steady state solves (mu u')' = -rho g with mu = rho nu
+    across the diffuse interface.  Pins the viscous correction F_mu and the
+    body force F_b = rho g (without F_mu the profile is the single-phase
+    parabola, 6.5 % away)."""
+    H, xi, tau, ga, rH, rL = 24, 4.0, 0.8, 1e-5, 1.0, 0.1
+    nu = (tau - 0.5) / 3
+    grid = P.Grid(1, H, 1, (True, False, True))
+    y = np.arange(H) + 0.5
+    phi0 = 0.5 + 0.5 * np.tanh(2 * (12 - y) / xi)
+    prm = P.OracleParams(tau, tau, 0.02, xi, 0.0, rH, rL, (ga, 0, 0))
+    h, g = _run(grid, prm, phi0, np.zeros((3, H)), np.zeros(H), 6000)
+    _, u, _ = P.moments(grid, prm, h, g)
+    yy = np.linspace(0, H, 20001)
+    ph = 0.5 + 0.5 * np.tanh(2 * (12 - yy) / xi)
+    rho = rL + ph * (rH - rL)
+    mu = rho * nu
+    S = cumulative_trapezoid(-rho * ga, yy, initial=0)
+    I1 = cumulative_trapezoid(S / mu, yy, initial=0)
+    I2 = cumulative_trapezoid(1 / mu, yy, initial=0)
+    uref = np.interp(y, yy, I1 - I1[-1] / I2[-1] * I2)
+    assert np.abs(u[0].numpy() - uref).max() / uref.max() < 0.025
+
+
+@pytest.mark.slow
+def test_laplace_pressure_of_a_static_drop():
+    """Heavy drop (R = 7) in a light phase (density ratio 1000): the pressure
+    p = p* rho c_s^2 jumps by 2 sigma / R.  Pins beta = 12 sigma/xi,
+    kappa = 3 sigma xi / 2, F_s = mu_phi grad phi and the sign of F_p."""
+    n, R, xi, sigma, rL = 24, 7.0, 4.0, 1e-3, 1e-3
+    grid = P.Grid(n, n, n, (True, True, True))
+    z, y, x = np.meshgrid(*(np.arange(n) + 0.5,) * 3, indexing="ij")
+    r = np.sqrt((x - n / 2) ** 2 + (y - n / 2) ** 2 + (z - n / 2) ** 2)
+    prm = P.OracleParams(0.8, 0.8, 0.05, xi, sigma, 1.0, rL, (0, 0, 0))
+    h, g = _run(grid, prm, 0.5 + 0.5 * np.tanh(2 * (R - r) / xi), np.zeros((3, n, n, n)),
+                np.zeros((n, n, n)), 800)
+    phi, u, ps = P.moments(grid, prm, h, g)
+    p = (ps * (rL + phi * (1 - rL)) / 3).numpy().reshape(n, n, n)
+    dp = p[r < R - 4].mean() - p[r > R + 5].mean()
+    assert abs(dp / A.laplace_jump(sigma, R) - 1) < 0.05
+
+
+def _capillary_first_minimum(L, T):
+    Re, rH, rL = 10.0, 1.0, 1e-3
+    k = 2 * math.pi / L
+    w0 = 2 * math.pi / T
+    sigma = w0 ** 2 * (rH + rL) / k ** 3
+    a0 = 0.01 * L
+    nu = a0 * w0 * L / Re
+    wl = W.capillary_wave(L, L, 1, depth=L / 2, amplitude=a0, xi=4.0, noise=0.0,
+                          params=W.Params(tau_H=3 * nu + 0.5, tau_L=3 * nu + 0.5,
+                                          mobility=0.02, sigma=sigma))
+    grid = P.Grid(L, L, 1, wl.periodic)
+    prm = P.OracleParams.from_workload(wl.params)
+    h, g = P.init_equilibrium(grid, wl.phi0, wl.u0, wl.pstar0)
+    ts, amps = [], []
+    n = int(0.7 * T)
+    for s in range(n + 1):
+        if s % 10 == 0:
+            ts.append(s)
+            amps.append(P.amplitude(grid, h, L / 2).item())
+        if s < n:
+            h, g = P.step(grid, prm, h, g)
+    ts, amps = np.array(ts), np.array(amps)
+    ref = A.prosperetti_amplitude(ts, amps[0], nu, k, w0, rH, rL)
+    i, j = np.argmin(amps), np.argmin(ref)
+    return ts[i] / ts[j], amps[i] / ref[j]
+
+
+@pytest.mark.slow
+def test_capillary_wave_converges_towards_prosperetti():
+    """Standing capillary wave (paper sec. capillary wave: density ratio 1000,
+    equal kinematic viscosities, Re = 10, a0 = 0.01 L, M = 0.02) against
+    Prosperetti's amplitude a(t): the time and depth of the first minimum
+    approach the analytic ones as L grows at fixed xi (the paper's
+    convergence setting)."""
+    t32, a32 = _capillary_first_minimum(32, 1500)
+    t48, a48 = _capillary_first_minimum(48, 2000)
+    assert abs(t48 - 1) < 0.12 and abs(a48 - 1) < 0.15
+    assert abs(t48 - 1) < abs(t32 - 1)
+    assert abs(a48 - 1) < abs(a32 - 1)
