@@ -1,0 +1,170 @@
+"""Benchmark of the coupled phase-field LBM step on one MI355X.
+
+A "step" is one time step of the whole hot path over the lattice: the fused
+collide-and-stream kernel of both populations (D3Q15 phase field + D3Q27
+hydrodynamics, forces, stencils, bounce-back) followed by the phase-field
+update.  The headline workload is the rising-bubble lattice 128 x 512 x 128
+(8.4 M cells, six bounce-back faces) in FP32; the line also carries the FP64
+and FP16-storage forms and the reverse-mode cost.
+
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-forms]
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled PFLBM MLUPS & %HBM roofline; FP32 vs FP16-store; adjoint/fwd cost"
+HBM_PEAK_GBPS = 8000.0
+# algorithmic bytes per cell of the collide-and-stream kernel: read + write
+# 15 + 27 populations once, read phi once (the phi-update kernel adds the one
+# phi write of the step's 344 B (FP32) / 688 B (FP64) / 176 B (FP16 storage))
+CELL_KERNEL_BYTES = {"fp64": 42 * 8 * 2 + 8, "fp32": 42 * 4 * 2 + 4, "fp16s": 42 * 2 * 2 + 4}
+STEP_BYTES = {"fp64": 688, "fp32": 344, "fp16s": 176}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_form(wl, precision, steps, warmup, collision="mrt"):
+    import torch
+
+    from paper_2206_11637_amd.sim import from_workload
+    sim = from_workload(wl, precision=precision, collision=collision)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    cell_ms, phi_ms, total_ms = sim.profile_step(steps)
+    t1.record()
+    torch.cuda.synchronize()
+    wall_ms = t0.elapsed_time(t1)
+    r = sim.reduce()
+    cells = wl.cells
+    mlups = cells * steps / (wall_ms * 1e-3) / 1e6
+    cell_avg = cell_ms / steps
+    achieved = CELL_KERNEL_BYTES[precision] * cells / (cell_avg * 1e-3) / 1e9
+    out = dict(mlups=mlups, ms_per_step=wall_ms / steps, cell_kernel_ms=cell_avg,
+               phi_kernel_ms=phi_ms / steps, cell_kernel_GBps=achieved,
+               cell_kernel_frac=achieved / HBM_PEAK_GBPS,
+               effective_GBps=mlups * STEP_BYTES[precision] / 1e3,
+               effective_frac=mlups * STEP_BYTES[precision] / 1e3 / HBM_PEAK_GBPS,
+               mass=r[0])
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline():
+    """The FP64 oracle on a bounded sample of the same workload (a z-slab of
+    the rising-bubble lattice with its walls), timed on the host cores."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import pflbm as OP
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+    threads = min(threads, 16)
+    torch.set_num_threads(threads)
+    wl = W.config1()
+    z0, z1 = 56, 72
+    grid = OP.Grid(wl.nx, wl.ny, z1 - z0, (False, False, False))
+    prm = OP.OracleParams.from_workload(wl.params, "mrt")
+    h, g = OP.init_equilibrium(grid, wl.phi0[z0:z1], wl.u0[:, z0:z1], wl.pstar0[z0:z1])
+    h, g = OP.step(grid, prm, h, g)   # first step builds the neighbour tables
+    nsteps = 8
+    t = time.perf_counter()
+    for _ in range(nsteps):
+        h, g = OP.step(grid, prm, h, g)
+    dt = time.perf_counter() - t
+    cells = grid.N
+    return {"value": cells * nsteps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"rising-bubble lattice cut to z in [{z0},{z1}) ({wl.nx}x{wl.ny}x{z1 - z0} "
+                      f"cells, walls on all faces), FP64 MRT, {nsteps} timed steps, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU slab "
+              "decomposition is a design, not an implementation); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("bench: rising bubble 128x512x128 fp32 mrt")
+    wl1 = W.config1()
+    main_form = time_form(wl1, "fp32", args.steps, args.warmup)
+    log(f"  fp32: {main_form['mlups']:.0f} MLUPS")
+    forms = {}
+    if not args.no_forms:
+        log("bench: rising bubble fp64")
+        forms["fp64_rising_bubble_128x512x128"] = time_form(wl1, "fp64", max(args.steps // 2, 10),
+                                                            args.warmup)
+        del wl1
+        log("bench: drop impact 384^3 fp32 and fp16 storage")
+        wl2 = W.config2()
+        forms["fp32_drop_impact_384^3"] = time_form(wl2, "fp32", max(args.steps // 2, 10),
+                                                    args.warmup)
+        forms["fp16s_drop_impact_384^3"] = time_form(wl2, "fp16s", max(args.steps // 2, 10),
+                                                     args.warmup)
+        del wl2
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        cpu = cpu_baseline()
+    line = {
+        "metric": METRIC,
+        "value": round(main_form["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_form["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rising_bubble_128x512x128", "cells": 128 * 512 * 128,
+                   "lattices": "D3Q15+D3Q27", "collision": "mrt", "storage": "fp32",
+                   "boundaries": "bounce-back on all faces"},
+        "roofline": {"bound": "hbm", "achieved": round(main_form["cell_kernel_GBps"], 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(main_form["cell_kernel_frac"], 4), "traffic": None,
+                     "kernel": "k_cell (fused collide-and-stream)",
+                     "bytes_per_cell": CELL_KERNEL_BYTES["fp32"]},
+        "step_effective": {"bytes_per_cell": STEP_BYTES["fp32"],
+                           "GBps": round(main_form["effective_GBps"], 1),
+                           "frac": round(main_form["effective_frac"], 4),
+                           "phi_kernel_ms": round(main_form["phi_kernel_ms"], 4),
+                           "cell_kernel_ms": round(main_form["cell_kernel_ms"], 4)},
+        "cpu_baseline": cpu,
+        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                  for k, v in forms.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

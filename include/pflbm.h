@@ -1,0 +1,215 @@
+/*
+ * pflbm.h -- C ABI of the MI355X (gfx950) coupled phase-field lattice Boltzmann step.
+ *
+ * The method is the conservative Allen-Cahn phase-field LBM compared in
+ * Schwarzmeier et al., "Comparison of free-surface and conservative
+ * Allen-Cahn phase-field lattice Boltzmann method" (arXiv:2206.11637),
+ * sec. "Conservative Allen-Cahn model":
+ *   - phase-field PDFs h_i on D3Q15 (eq. lb_interface), phi = sum_i h_i
+ *     (eq. zeroth_moment_phase), relaxation time tau_phi = M / c_s^2
+ *     (eq. pflbm-tau), counter-term F^phi = 4 phi (1 - phi)/xi n applied with
+ *     Guo forcing;
+ *   - hydrodynamic PDFs g_i on D3Q27 (velocity-based, incompressible
+ *     equilibrium eq. feq with rho_0 = 1), p* = sum_i g_i
+ *     (eq. zeroth_moment_hydro), total force F = F_s + F_b + F_p + F_mu with
+ *     F_s = mu_phi grad phi, F_b = rho g, F_p = -p* c_s^2 (rho_H - rho_L) grad phi,
+ *     F_mu = nu (rho_H - rho_L) [grad u + grad u^T] grad phi taken from
+ *     non-equilibrium moments; rho(phi) and tau(phi) linear in phi;
+ *   - weighted-orthogonal MRT (eq. mrt) or BGK (eq. BGK) collisions,
+ *     streaming (eq. streaming) with halfway bounce-back walls.
+ *
+ * Conventions for every entry point:
+ *   - Lattice units: dx = dt = 1, c_s^2 = 1/3.
+ *   - Grid: nx * ny * nz cells, cell index idx = x + nx * (y + ny * z).
+ *     Scalar fields are N = nx*ny*nz values in that order; vector fields are
+ *     three such planes (x, y, z components).  Populations are
+ *     structure-of-arrays: population i of cell idx at [i * N + idx].
+ *   - Non-periodic axes carry halfway bounce-back walls on the box faces; a
+ *     solid mask (1 = solid) adds interior solids.  A solid or out-of-box
+ *     neighbour contributes the cell's own phi to the grad/lap stencils.
+ *   - Memory: the caller owns every device buffer, including the workspace
+ *     the context lives in.  The library never allocates device memory and
+ *     never frees caller memory.  Pointers passed in must stay valid while
+ *     the context uses them.  "d_" marks device pointers, "host" host ones.
+ *   - Streams: all work is enqueued on the stream given at creation, in
+ *     order.  Only pflbm_reduce, pflbm_adjoint_grads and pflbm_sync wait
+ *     for the stream.
+ *   - Errors: every call returns a pflbm_status; nothing aborts.  Invalid
+ *     arguments return PFLBM_ERR_ARG with no work enqueued.  HIP launch or
+ *     runtime errors return PFLBM_ERR_HIP.  pflbm_last_error() holds a message.
+ *   - Threads: one context must not be used from two threads at once.
+ */
+#ifndef PFLBM_H
+#define PFLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pflbm_ctx pflbm_ctx;
+
+typedef enum {
+  PFLBM_OK = 0,
+  PFLBM_ERR_ARG = 1,         /* invalid argument; nothing was enqueued            */
+  PFLBM_ERR_STATE = 2,       /* call not valid in the context's current state     */
+  PFLBM_ERR_HIP = 3,         /* HIP runtime or launch error                       */
+  PFLBM_ERR_UNSTABLE = 4,    /* a reduction returned NaN/Inf                      */
+  PFLBM_ERR_UNSUPPORTED = 5  /* combination of options not built                  */
+} pflbm_status;
+
+typedef enum {
+  PFLBM_FP64 = 0,        /* FP64 populations, FP64 arithmetic                     */
+  PFLBM_FP32 = 1,        /* FP32 populations, FP32 arithmetic                     */
+  PFLBM_FP32_FP16S = 2   /* FP32 arithmetic, populations stored as FP16 of
+                            (f_i - s_i) * 2^k; s_i = FP16-rounded w_i for h,
+                            0 for g; k per lattice from fp16_scale_log2          */
+} pflbm_precision;
+
+typedef enum { PFLBM_BGK = 0, PFLBM_MRT = 1 } pflbm_collision;
+
+typedef struct {
+  int32_t nx, ny, nz;     /* cells per axis, each >= 1                            */
+  uint32_t periodic;      /* bit0 x, bit1 y, bit2 z; clear bit = walls on that axis */
+  int32_t precision;      /* pflbm_precision                                      */
+  int32_t collision;      /* pflbm_collision                                      */
+  int32_t has_mask;       /* 1: pflbm_set_mask must be called before init          */
+} pflbm_desc;
+
+typedef struct {
+  double tau_H, tau_L;    /* hydrodynamic relaxation times (> 1/2); nu = (tau - 1/2)/3,
+                             tau(phi) = tau_L + phi (tau_H - tau_L)                */
+  double mobility;        /* M > 0; phase-field rate omega_phi = 1 / (3 M + 1/2)   */
+  double xi;              /* interface width > 0; +inf switches the counter-term
+                             and the chemical potential off                        */
+  double sigma;           /* surface tension >= 0; mu_phi = 4 beta phi (phi-1)(phi-1/2)
+                             - kappa lap phi, beta = 12 sigma/xi, kappa = 3 sigma xi/2 */
+  double rho_H, rho_L;    /* heavy / light densities (> 0); rho(phi) linear        */
+  double g[3];            /* body acceleration                                     */
+  double s_high;          /* MRT rate of moments of degree >= 3 (0 < s < 2)        */
+  double fp16_scale_log2[2]; /* FP16S storage exponents k for h and g (integers,
+                             |k| <= 24); ignored by the other precisions          */
+} pflbm_params;
+
+/* Bytes of device workspace for a context with this description (256-aligned
+ * regions: populations, two phi buffers, mask, reduction partials).  Returns 0
+ * if the description is invalid. */
+size_t pflbm_workspace_bytes(const pflbm_desc* desc);
+
+/* Creates a host-side context that uses d_workspace (>= pflbm_workspace_bytes,
+ * 256-byte aligned) and enqueues everything on hip_stream (a hipStream_t, NULL =
+ * the null stream).  Parameters default to those of a capillary-wave case
+ * until pflbm_set_params is called.  *out receives the context. */
+pflbm_status pflbm_create(const pflbm_desc* desc, void* d_workspace, size_t bytes,
+                          void* hip_stream, pflbm_ctx** out);
+
+/* Frees the host-side context only (the workspace stays the caller's). */
+pflbm_status pflbm_destroy(pflbm_ctx* ctx);
+
+/* Validates and sets the physical parameters (tau > 1/2, M > 0, xi > 0,
+ * sigma >= 0, rho > 0, 0 < s_high < 2).  Takes effect for the next step. */
+pflbm_status pflbm_set_params(pflbm_ctx* ctx, const pflbm_params* params);
+
+/* Copies an N-byte solid mask (1 = solid, 0 = fluid) into the workspace
+ * (device-to-device, asynchronous).  Only for contexts created with has_mask. */
+pflbm_status pflbm_set_mask(pflbm_ctx* ctx, const uint8_t* d_solid);
+
+/* Equilibrium initialisation: h_i = phi0 w_i [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u],
+ * g_i = w_i [p*0 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u], zero in solids, then
+ * phi = sum_i h_i.  d_phi0 [N], d_u0 [3][N], d_pstar0 [N] (FP64; d_u0 or
+ * d_pstar0 may be NULL for zero).  Resets the step counter to 0. */
+pflbm_status pflbm_init_equilibrium(pflbm_ctx* ctx, const double* d_phi0,
+                                    const double* d_u0, const double* d_pstar0);
+
+/* Advances nsteps >= 0 time steps (collide + stream of h and g, then the phi
+ * update), asynchronously. */
+pflbm_status pflbm_step(pflbm_ctx* ctx, int64_t nsteps);
+
+/* Cell moments of the current state as FP64: phi [N], u [3][N] (the
+ * force-corrected velocity u = j + F/(2 rho)), p* [N]; zero in solids.  Any
+ * output may be NULL. */
+pflbm_status pflbm_read_moments(pflbm_ctx* ctx, double* d_phi, double* d_u, double* d_pstar);
+
+/* The current phase field phi^n = sum_i h_i^n as FP64 [N] (cheap; no forces). */
+pflbm_status pflbm_read_phi(pflbm_ctx* ctx, double* d_phi);
+
+/* Post-streaming populations in natural order, decoded to FP64:
+ * d_h [15][N], d_g [27][N] in the library's velocity order (pflbm_lattice). */
+pflbm_status pflbm_read_populations(pflbm_ctx* ctx, double* d_h, double* d_g);
+
+/* FP64 sums over fluid cells: out_host = {sum phi, sum p*, sum j_x, sum j_y,
+ * sum j_z} with j = sum_i c_i g_i.  Deterministic (fixed reduction order).
+ * Waits for the stream.  Returns PFLBM_ERR_UNSTABLE if any is NaN/Inf. */
+pflbm_status pflbm_reduce(pflbm_ctx* ctx, double out_host[5]);
+
+/* Bytes of one saved state (populations + phi field, storage precision). */
+size_t pflbm_state_bytes(const pflbm_ctx* ctx);
+
+/* Copies the state to / from d_buf (device-to-device, asynchronous).  The
+ * step count is not part of the buffer: load takes it explicitly (its parity
+ * selects the in-place streaming layout). */
+pflbm_status pflbm_save_state(pflbm_ctx* ctx, void* d_dst);
+pflbm_status pflbm_load_state(pflbm_ctx* ctx, const void* d_src, int64_t step_count);
+
+/* Steps taken since the last init or load. */
+int64_t pflbm_step_count(const pflbm_ctx* ctx);
+
+/* Advances nsteps like pflbm_step while timing every kernel with HIP events
+ * recorded on the context's stream between consecutive launches (no host
+ * synchronisation inside the loop); out_ms_host receives {summed durations of
+ * the collide-and-stream kernel, summed durations of the phi-update kernel,
+ * total elapsed time} in milliseconds.  Waits for the stream at the end. */
+pflbm_status pflbm_profile_step(pflbm_ctx* ctx, int64_t nsteps, double out_ms_host[3]);
+
+/* Waits for all work on the context's stream. */
+pflbm_status pflbm_sync(pflbm_ctx* ctx);
+
+/* Host copy of the library's velocity set for q = 15 (D3Q15) or 27 (D3Q27):
+ * c_out [q][3] integers, w_out [q] weights.  Either may be NULL. */
+pflbm_status pflbm_lattice(int32_t q, int32_t* c_out, double* w_out);
+
+/* ---------------------------------------------------------------------------
+ * Reverse mode (adjoint) of the step, for gradients of a loss of the phase
+ * field with respect to the mobility M, the surface tension sigma and the
+ * initial phase field phi0.  The adjoint state lambda holds dL/dh and dL/dg of
+ * one time level.  Arithmetic is FP64 for PFLBM_FP64 contexts and FP32
+ * otherwise; the parameter gradients are accumulated in FP64.  With FP16S
+ * storage the quantisation is treated as the identity.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of the adjoint workspace for this description (0 if invalid). */
+size_t pflbm_adjoint_workspace_bytes(const pflbm_desc* desc);
+
+/* Attaches an adjoint workspace and clears lambda and the gradient sums. */
+pflbm_status pflbm_adjoint_attach(pflbm_ctx* ctx, void* d_adj_workspace, size_t bytes);
+
+/* Clears lambda and the gradient sums (start of a new backward pass). */
+pflbm_status pflbm_adjoint_reset(pflbm_ctx* ctx);
+
+/* Adds dL/dphi^n (FP64 [N], the loss's direct sensitivity to the phase field
+ * of the current adjoint time level n) into lambda. */
+pflbm_status pflbm_adjoint_inject_phi(pflbm_ctx* ctx, const double* d_dl_dphi);
+
+/* One reverse step: lambda^{n+1} -> lambda^n through the step n -> n+1,
+ * using the primal state of level n (a buffer written by pflbm_save_state
+ * when the step count was n), and adds this step's contributions to dL/dM
+ * and dL/dsigma. */
+pflbm_status pflbm_adjoint_step(pflbm_ctx* ctx, const void* d_state_n, int64_t n);
+
+/* Reverse of pflbm_init_equilibrium for phi0: d_dphi0 [N] (FP64) receives
+ * dL/dphi0 = sum_i lambda_h,i Gamma_i(u0), with u0 (FP64 [3][N], NULL = 0)
+ * the velocity the state was initialised with; zero in solids. */
+pflbm_status pflbm_adjoint_init(pflbm_ctx* ctx, const double* d_u0, double* d_dphi0);
+
+/* out_host = {dL/dM, dL/dsigma} accumulated since attach/reset.  Waits. */
+pflbm_status pflbm_adjoint_grads(pflbm_ctx* ctx, double out_host[2]);
+
+const char* pflbm_status_string(pflbm_status s);
+const char* pflbm_last_error(const pflbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFLBM_H */

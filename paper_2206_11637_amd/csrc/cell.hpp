@@ -1,0 +1,221 @@
+// Per-cell arithmetic of the coupled phase-field LBM step (registers only).
+//
+// Paper sec. "Conservative Allen-Cahn model" (arXiv:2206.11637):
+//   phi = sum h_i (eq. zeroth_moment_phase); rho(phi), tau(phi) linear in phi;
+//   counter-term 4 phi (1 - phi)/xi n (Guo forcing on the phase field);
+//   p* = sum g_i (eq. zeroth_moment_hydro); F = F_s + F_b + F_p + F_mu with
+//   F_s = mu_phi grad phi, F_b = rho g, F_p = -p* c_s^2 (rho_H - rho_L) grad phi
+//   and F_mu from the non-equilibrium second moment of g (end of the LBE
+//   section); incompressible equilibrium (eq. feq, rho_0 = 1); MRT (eq. mrt).
+//
+// MRT here is written in its projected form.  With one rate per polynomial
+// degree of a weighted-orthogonal moment basis (s_lo for degree <= 2, s_hi
+// above), M^-1 S M Delta = s_hi Delta + (s_lo - s_hi) P Delta, where P is the
+// weighted projection onto quadratic polynomials of c:
+//   (P Delta)_i = w_i [a0 + 3 c_i.a1 + 9/2 (c_i c_i - I/3) : A2],
+//   a0 = sum Delta, a1 = sum c Delta, A2 = sum (c c - I/3) Delta.
+// The moments of the equilibria are known in closed form (4th-order isotropic
+// lattices), so a0 = 0, and a1, A2 follow from a handful of moments of the
+// pre-collision populations instead of a q x q product.  BGK is s_hi = s_lo.
+#pragma once
+#include "lattice.hpp"
+
+namespace pflbm {
+
+template <typename R>
+struct Phys {
+  R tau_L, dtau;      // tau(phi) = tau_L + phi dtau
+  R rho_L, drho;      // rho(phi) = rho_L + phi drho
+  R theta_k;          // 4/xi (0 when xi = inf):  theta = theta_k phi (1 - phi)
+  R beta4;            // 4 beta = 48 sigma / xi
+  R kappa;            // 3 sigma xi / 2
+  R gx, gy, gz;       // body acceleration
+  R omega_phi;        // 1 / (3 M + 1/2)
+  R s_high;           // rate of degree >= 3 moments (MRT)
+  R eps2;             // regularisation of |grad phi| in n
+};
+
+// second-moment tensor of a population set, symmetric storage xx yy zz xy xz yz
+template <typename R>
+struct Sym { R xx, yy, zz, xy, xz, yz; };
+
+template <typename R>
+__device__ __forceinline__ R sum_h(const R (&h)[Q_H]) {
+  R s = h[0];
+#pragma unroll
+  for (int i = 1; i < Q_H; ++i) s += h[i];
+  return s;
+}
+
+// Cell state after the force prologue (everything the collisions need).
+template <typename R>
+struct CellState {
+  R phi, rho, omega, theta, nx, ny, nz;
+  R p, jx, jy, jz;
+  R ux, uy, uz;      // force-corrected velocity u = j + F/(2 rho)
+  R Fx, Fy, Fz;      // total force
+  Sym<R> Pi;         // sum c c g
+};
+
+// S1-S11: moments, chemical potential, forces and velocity of one cell.
+template <typename R>
+__device__ __forceinline__ void prologue(const R (&h)[Q_H], const R (&g)[Q_G], R Gx, R Gy,
+                                         R Gz, R lap, const Phys<R>& P, CellState<R>& c) {
+  const R phi = sum_h(h);
+  c.phi = phi;
+  c.rho = P.rho_L + phi * P.drho;
+  c.omega = R(1) / (P.tau_L + phi * P.dtau);
+  c.theta = P.theta_k * phi * (R(1) - phi);
+  const R ninv = R(1) / sqrt(Gx * Gx + Gy * Gy + Gz * Gz + P.eps2);
+  c.nx = Gx * ninv;
+  c.ny = Gy * ninv;
+  c.nz = Gz * ninv;
+  const R mu = P.beta4 * phi * (phi - R(1)) * (phi - R(0.5)) - P.kappa * lap;
+
+  R p = R(0), jx = R(0), jy = R(0), jz = R(0);
+  Sym<R> Pi{R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    const Dir d = cg(i);
+    const R v = g[i];
+    p += v;
+    if (d.x) jx += d.x > 0 ? v : -v;
+    if (d.y) jy += d.y > 0 ? v : -v;
+    if (d.z) jz += d.z > 0 ? v : -v;
+    if (d.x) Pi.xx += v;
+    if (d.y) Pi.yy += v;
+    if (d.z) Pi.zz += v;
+    if (d.x * d.y) Pi.xy += (d.x * d.y) > 0 ? v : -v;
+    if (d.x * d.z) Pi.xz += (d.x * d.z) > 0 ? v : -v;
+    if (d.y * d.z) Pi.yz += (d.y * d.z) > 0 ? v : -v;
+  }
+  c.p = p;
+  c.jx = jx;
+  c.jy = jy;
+  c.jz = jz;
+  c.Pi = Pi;
+
+  // F_s + F_p share the direction grad phi; F_b = rho g
+  const R cgrad = mu - p * (R(1) / R(3)) * P.drho;
+  const R F0x = cgrad * Gx + c.rho * P.gx;
+  const R F0y = cgrad * Gy + c.rho * P.gy;
+  const R F0z = cgrad * Gz + c.rho * P.gz;
+  const R inv2rho = R(0.5) / c.rho;
+  const R u1x = jx + F0x * inv2rho;
+  const R u1y = jy + F0y * inv2rho;
+  const R u1z = jz + F0z * inv2rho;
+  // Pi_neq with the equilibrium at u': sum c c g^eq(p*, u') = p*/3 I + u' u'^T
+  const R p3 = p * (R(1) / R(3));
+  const R nxx = Pi.xx - p3 - u1x * u1x;
+  const R nyy = Pi.yy - p3 - u1y * u1y;
+  const R nzz = Pi.zz - p3 - u1z * u1z;
+  const R nxy = Pi.xy - u1x * u1y;
+  const R nxz = Pi.xz - u1x * u1z;
+  const R nyz = Pi.yz - u1y * u1z;
+  const R fmu = -(R(1) - R(0.5) * c.omega) * P.drho;
+  c.Fx = F0x + fmu * (nxx * Gx + nxy * Gy + nxz * Gz);
+  c.Fy = F0y + fmu * (nxy * Gx + nyy * Gy + nyz * Gz);
+  c.Fz = F0z + fmu * (nxz * Gx + nyz * Gy + nzz * Gz);
+  c.ux = jx + c.Fx * inv2rho;
+  c.uy = jy + c.Fy * inv2rho;
+  c.uz = jz + c.Fz * inv2rho;
+}
+
+template <typename R>
+__device__ __forceinline__ R dot(Dir d, R x, R y, R z) {
+  R r = R(0);
+  if (d.x) r += d.x > 0 ? x : -x;
+  if (d.y) r += d.y > 0 ? y : -y;
+  if (d.z) r += d.z > 0 ? z : -z;
+  return r;
+}
+
+// (c c - I/3) : A for symmetric A
+template <typename R>
+__device__ __forceinline__ R hermite2(Dir d, const Sym<R>& A) {
+  R r = -(A.xx + A.yy + A.zz) * (R(1) / R(3));
+  if (d.x) r += A.xx;
+  if (d.y) r += A.yy;
+  if (d.z) r += A.zz;
+  if (d.x * d.y) r += (d.x * d.y > 0) ? R(2) * A.xy : -R(2) * A.xy;
+  if (d.x * d.z) r += (d.x * d.z > 0) ? R(2) * A.xz : -R(2) * A.xz;
+  if (d.y * d.z) r += (d.y * d.z > 0) ? R(2) * A.yz : -R(2) * A.yz;
+  return r;
+}
+
+// S12-S13: hydrodynamic collision in place.
+template <typename R, bool MRT>
+__device__ __forceinline__ void collide_g(R (&g)[Q_G], const CellState<R>& c, const Phys<R>& P) {
+  const R uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
+  const R om = c.omega;
+  const R fk = (R(1) - R(0.5) * om) * R(3) / c.rho;   // (1 - om/2) 3 F / rho per w c.F
+  const R base = c.p - R(1.5) * uu;
+  const R shi = MRT ? P.s_high : om;
+  const R dlo = om - shi;
+  // moments of Delta = g^eq - g: a1 = u - j, A2 = p/3 I + u u - Pi
+  const R a1x = c.ux - c.jx, a1y = c.uy - c.jy, a1z = c.uz - c.jz;
+  const R p3 = c.p * (R(1) / R(3));
+  Sym<R> A2{p3 + c.ux * c.ux - c.Pi.xx, p3 + c.uy * c.uy - c.Pi.yy, p3 + c.uz * c.uz - c.Pi.zz,
+            c.ux * c.uy - c.Pi.xy, c.ux * c.uz - c.Pi.xz, c.uy * c.uz - c.Pi.yz};
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    const Dir d = cg(i);
+    const R w = R(wg(i));
+    const R cu = dot(d, c.ux, c.uy, c.uz);
+    const R geq = w * (base + cu * (R(3) + R(4.5) * cu));
+    const R force = w * fk * dot(d, c.Fx, c.Fy, c.Fz);
+    R v = g[i] + shi * (geq - g[i]) + force;
+    if (MRT) v += dlo * w * (R(3) * dot(d, a1x, a1y, a1z) + R(4.5) * hermite2(d, A2));
+    g[i] = v;
+  }
+}
+
+// S14-S15: phase-field collision in place (needs u from the hydro prologue).
+template <typename R, bool MRT>
+__device__ __forceinline__ void collide_h(R (&h)[Q_H], const CellState<R>& c, const Phys<R>& P) {
+  const R uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
+  const R om = P.omega_phi;
+  const R fk = (R(1) - R(0.5) * om) * c.theta;
+  const R shi = MRT ? P.s_high : om;
+  const R dlo = om - shi;
+  const R phi = c.phi;
+  Sym<R> A2{R(0), R(0), R(0), R(0), R(0), R(0)};
+  R a1x = R(0), a1y = R(0), a1z = R(0);
+  if (MRT) {
+    R jx = R(0), jy = R(0), jz = R(0);
+    Sym<R> Pi{R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 0; i < Q_H; ++i) {
+      const Dir d = ch(i);
+      const R v = h[i];
+      if (d.x) { jx += d.x > 0 ? v : -v; Pi.xx += v; }
+      if (d.y) { jy += d.y > 0 ? v : -v; Pi.yy += v; }
+      if (d.z) { jz += d.z > 0 ? v : -v; Pi.zz += v; }
+      if (d.x * d.y) Pi.xy += (d.x * d.y > 0) ? v : -v;
+      if (d.x * d.z) Pi.xz += (d.x * d.z > 0) ? v : -v;
+      if (d.y * d.z) Pi.yz += (d.y * d.z > 0) ? v : -v;
+    }
+    // moments of h^eq: phi u, phi (I/3 + u u)
+    a1x = phi * c.ux - jx;
+    a1y = phi * c.uy - jy;
+    a1z = phi * c.uz - jz;
+    const R p3 = phi * (R(1) / R(3));
+    A2 = Sym<R>{p3 + phi * c.ux * c.ux - Pi.xx, p3 + phi * c.uy * c.uy - Pi.yy,
+                p3 + phi * c.uz * c.uz - Pi.zz, phi * c.ux * c.uy - Pi.xy,
+                phi * c.ux * c.uz - Pi.xz, phi * c.uy * c.uz - Pi.yz};
+  }
+  const R base = R(1) - R(1.5) * uu;
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    const Dir d = ch(i);
+    const R w = R(wh(i));
+    const R cu = dot(d, c.ux, c.uy, c.uz);
+    const R heq = w * phi * (base + cu * (R(3) + R(4.5) * cu));
+    const R force = w * fk * dot(d, c.nx, c.ny, c.nz);
+    R v = h[i] + shi * (heq - h[i]) + force;
+    if (MRT) v += dlo * w * (R(3) * dot(d, a1x, a1y, a1z) + R(4.5) * hermite2(d, A2));
+    h[i] = v;
+  }
+}
+
+}  // namespace pflbm

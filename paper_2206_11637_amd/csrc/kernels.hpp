@@ -1,0 +1,504 @@
+// Forward kernels of the coupled phase-field LBM step on gfx950.
+//
+// Data layout in HBM (all structure-of-arrays, x fastest):
+//   h[i * N + idx], i < 15       phase-field populations (storage type S)
+//   g[i * N + idx], i < 27       hydrodynamic populations
+//   phi[2][N]                    phase field, double-buffered (compute type R)
+//   mask[N]                      optional solids (1 = solid)
+//
+// Streaming is the in-place AA pattern (one population buffer per lattice):
+//   even step: read own slots f[i][x], write f*_i into own slot f[opp i][x];
+//   odd step:  read f_i(x) from f[opp i][x - c_i] (or f[i][x] when x - c_i is
+//              a wall/solid: the value bounced back there), write f*_i into
+//              f[i][x + c_i] (or f[opp i][x] when x + c_i is a wall/solid).
+// Every slot is read and written by exactly one cell per step, which makes
+// the update race-free without a second population buffer; halfway
+// bounce-back falls out of the redirected addresses (paper: streaming
+// eq. and bounce-back walls).  After an odd step the buffer holds the
+// natural layout f[i][x] = f_i(x).
+//
+// One thread per cell.  A block is a bx * by tile of one z plane (256
+// threads); it stages phi of the tile plus a one-cell halo on three planes in
+// LDS, where out-of-box and solid neighbours carry a sentinel.  The sentinel
+// both selects the wall rule of the phi stencils and tells the AA addressing
+// which neighbours are walls, so no mask read is needed on the hot path.
+//
+// Blocks are issued round-robin over the 8 XCDs; xcd_remap() renumbers them
+// so that each XCD walks one contiguous slab of tiles, keeping the halo and
+// neighbour-population reuse inside one XCD's L2.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "cell.hpp"
+#include "lattice.hpp"
+
+namespace pflbm {
+
+struct Geom {
+  int nx, ny, nz;
+  int px, py, pz;         // periodic flags
+  int bx, by;             // tile shape (bx * by == 256)
+  int tiles_x, tiles_y;
+  unsigned nblocks;       // tiles_x * tiles_y * nz
+  long long N;
+};
+
+// ---- storage codecs -------------------------------------------------------
+template <typename S>
+struct Store;
+template <>
+struct Store<double> {
+  using R = double;
+  __device__ static R ld(const double* p, R, R) { return *p; }
+  __device__ static void st(double* p, R v, R, R) { *p = v; }
+};
+template <>
+struct Store<float> {
+  using R = float;
+  __device__ static R ld(const float* p, R, R) { return *p; }
+  __device__ static void st(float* p, R v, R, R) { *p = v; }
+};
+// FP16 storage of (f - shift) * 2^k, decoded exactly into FP32
+template <>
+struct Store<_Float16> {
+  using R = float;
+  __device__ static R ld(const _Float16* p, R shift, R inv_scale) {
+    return static_cast<float>(*p) * inv_scale + shift;
+  }
+  __device__ static void st(_Float16* p, R v, R shift, R scale) {
+    *p = static_cast<_Float16>((v - shift) * scale);
+  }
+};
+
+template <typename R>
+struct Codec {
+  R sh_h[Q_H];            // shifts of h (0 unless FP16 storage)
+  R scale_h, inv_scale_h, scale_g, inv_scale_g;
+};
+
+template <typename R>
+__device__ __forceinline__ R sentinel() { return R(-1e30); }
+
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
+  const unsigned q = nb >> 3, r = nb & 7u, x = b & 7u, k = b >> 3;
+  return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+struct TileCoord { int x0, y0, z; };
+
+__device__ __forceinline__ TileCoord tile_of_block(const Geom& G) {
+  const unsigned L = xcd_remap(blockIdx.x, G.nblocks);
+  const unsigned tx = L % G.tiles_x;
+  const unsigned rest = L / G.tiles_x;
+  const unsigned ty = rest % G.tiles_y;
+  return TileCoord{int(tx) * G.bx, int(ty) * G.by, int(rest / G.tiles_y)};
+}
+
+// Neighbour coordinates with periodic wrap; returns false outside a wall.
+__device__ __forceinline__ bool wrap(int& v, int n, int periodic) {
+  if (v < 0) { if (!periodic) return false; v += n; }
+  else if (v >= n) { if (!periodic) return false; v -= n; }
+  return true;
+}
+
+// Stage phi of the tile + halo (3 planes) into LDS; sentinel for walls/solids.
+template <typename R, bool MASK>
+__device__ __forceinline__ void load_phi_tile(R* tile, const R* __restrict__ phi,
+                                              const unsigned char* __restrict__ mask,
+                                              const Geom& G, TileCoord t) {
+  const int TX = G.bx + 2, TY = G.by + 2, total = TX * TY * 3;
+  const int tid = threadIdx.x + threadIdx.y * G.bx;
+  for (int e = tid; e < total; e += 256) {
+    const int ix = e % TX, r = e / TX, iy = r % TY, iz = r / TY;
+    int X = t.x0 - 1 + ix, Y = t.y0 - 1 + iy, Z = t.z - 1 + iz;
+    R v = sentinel<R>();
+    if (wrap(X, G.nx, G.px) && wrap(Y, G.ny, G.py) && wrap(Z, G.nz, G.pz)) {
+      const long long id = X + (long long)G.nx * (Y + (long long)G.ny * Z);
+      if (!MASK || !mask[id]) v = phi[id];
+    }
+    tile[e] = v;
+  }
+}
+
+// Linear indices of the 3x3x3 neighbourhood (periodic wrap; out-of-box
+// entries are never dereferenced because the tile marks them as walls).
+struct Nbhd {
+  int xs[3];
+  long long ys[3], zs[3];
+  __device__ __forceinline__ long long at(int dx, int dy, int dz) const {
+    return xs[dx + 1] + ys[dy + 1] + zs[dz + 1];
+  }
+};
+
+__device__ __forceinline__ Nbhd make_nbhd(int x, int y, int z, const Geom& G) {
+  Nbhd n;
+  n.xs[0] = x == 0 ? G.nx - 1 : x - 1;
+  n.xs[1] = x;
+  n.xs[2] = x == G.nx - 1 ? 0 : x + 1;
+  const long long sy = G.nx, sz = (long long)G.nx * G.ny;
+  n.ys[0] = (y == 0 ? G.ny - 1 : y - 1) * sy;
+  n.ys[1] = y * sy;
+  n.ys[2] = (y == G.ny - 1 ? 0 : y + 1) * sy;
+  n.zs[0] = (z == 0 ? G.nz - 1 : z - 1) * sz;
+  n.zs[1] = z * sz;
+  n.zs[2] = (z == G.nz - 1 ? 0 : z + 1) * sz;
+  return n;
+}
+
+// Bit k of the result: neighbour in direction kC27[k] is a wall or solid.
+template <typename R>
+__device__ __forceinline__ unsigned wall_bits(const R* tile, int TX, int TY, int lx, int ly) {
+  unsigned b = 0;
+#pragma unroll
+  for (int k = 1; k < 27; ++k) {
+    const Dir d = cg(k);
+    const R v = tile[((1 + d.z) * TY + (ly + 1 + d.y)) * TX + (lx + 1 + d.x)];
+    if (v == sentinel<R>()) b |= 1u << k;
+  }
+  return b;
+}
+
+// grad phi and lap phi from the LDS tile (missing neighbours repeat phi(x)).
+template <typename R>
+__device__ __forceinline__ void stencil(const R* tile, int TX, int TY, int lx, int ly, R& Gx,
+                                        R& Gy, R& Gz, R& lap) {
+  const R p0 = tile[(TY + ly + 1) * TX + lx + 1];
+  Gx = Gy = Gz = lap = R(0);
+#pragma unroll
+  for (int k = 1; k < 27; ++k) {
+    const Dir d = cg(k);
+    const R v = tile[((1 + d.z) * TY + (ly + 1 + d.y)) * TX + (lx + 1 + d.x)];
+    const R diff = (v == sentinel<R>()) ? R(0) : v - p0;
+    const R w = R(wg(k));
+    if (d.x) Gx += (d.x > 0 ? w : -w) * diff;
+    if (d.y) Gy += (d.y > 0 ? w : -w) * diff;
+    if (d.z) Gz += (d.z > 0 ? w : -w) * diff;
+    lap += w * diff;
+  }
+  Gx *= R(3);
+  Gy *= R(3);
+  Gz *= R(3);
+  lap *= R(6);
+}
+
+// ---- population access (AA pattern) --------------------------------------
+template <typename S, bool ODD>
+__device__ __forceinline__ void load_pops(const S* __restrict__ H, const S* __restrict__ Gp,
+                                          long long N, long long idx, const Nbhd& nb,
+                                          unsigned walls, const Codec<typename Store<S>::R>& cd,
+                                          typename Store<S>::R (&h)[Q_H],
+                                          typename Store<S>::R (&g)[Q_G]) {
+  using St = Store<S>;
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    const int k = kH2G[i];
+    long long a = (long long)i * N + idx;
+    if (ODD) {
+      const Dir d = ch(i);
+      if (!(walls & (1u << nb27(-d.x, -d.y, -d.z))))
+        a = (long long)opp(i) * N + nb.at(-d.x, -d.y, -d.z);
+    }
+    (void)k;
+    h[i] = St::ld(H + a, cd.sh_h[i], cd.inv_scale_h);
+  }
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    long long a = (long long)i * N + idx;
+    if (ODD) {
+      const Dir d = cg(i);
+      if (!(walls & (1u << nb27(-d.x, -d.y, -d.z))))
+        a = (long long)opp(i) * N + nb.at(-d.x, -d.y, -d.z);
+    }
+    g[i] = St::ld(Gp + a, typename Store<S>::R(0), cd.inv_scale_g);
+  }
+}
+
+template <typename S, bool ODD>
+__device__ __forceinline__ void store_pops(S* __restrict__ H, S* __restrict__ Gp, long long N,
+                                           long long idx, const Nbhd& nb, unsigned walls,
+                                           const Codec<typename Store<S>::R>& cd,
+                                           const typename Store<S>::R (&h)[Q_H],
+                                           const typename Store<S>::R (&g)[Q_G]) {
+  using St = Store<S>;
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    long long a = (long long)opp(i) * N + idx;
+    if (ODD) {
+      const Dir d = ch(i);
+      if (!(walls & (1u << nb27(d.x, d.y, d.z)))) a = (long long)i * N + nb.at(d.x, d.y, d.z);
+    }
+    St::st(H + a, h[i], cd.sh_h[i], cd.scale_h);
+  }
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    long long a = (long long)opp(i) * N + idx;
+    if (ODD) {
+      const Dir d = cg(i);
+      if (!(walls & (1u << nb27(d.x, d.y, d.z)))) a = (long long)i * N + nb.at(d.x, d.y, d.z);
+    }
+    St::st(Gp + a, g[i], typename Store<S>::R(0), cd.scale_g);
+  }
+}
+
+template <typename S>
+struct CellArgs {
+  using R = typename Store<S>::R;
+  S* h;
+  S* g;
+  const R* phi;              // phi^n (stencil source)
+  const unsigned char* mask;
+  Geom geo;
+  Phys<R> P;
+  Codec<R> cd;
+  // outputs of the moments mode (FP64, may be null)
+  double* out_phi;
+  double* out_u;
+  double* out_p;
+};
+
+enum Mode { MODE_STEP = 0, MODE_MOMENTS = 1 };
+
+// Fused collide + stream of both lattices (MODE_STEP), or the cell moments
+// with the same force prologue (MODE_MOMENTS).
+template <typename S, bool MRT, bool ODD, bool MASK, int MODE>
+__global__ __launch_bounds__(256) void k_cell(CellArgs<S> a) {
+  using R = typename Store<S>::R;
+  extern __shared__ unsigned char smem_raw[];
+  R* tile = reinterpret_cast<R*>(smem_raw);
+  const Geom& G = a.geo;
+  const TileCoord t = tile_of_block(G);
+  load_phi_tile<R, MASK>(tile, a.phi, a.mask, G, t);
+  __syncthreads();
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const int TX = G.bx + 2, TY = G.by + 2;
+  const long long idx = x + (long long)G.nx * (y + (long long)G.ny * z);
+  if (tile[(TY + ly + 1) * TX + lx + 1] == sentinel<R>()) {   // solid cell
+    if (MODE == MODE_MOMENTS) {
+      if (a.out_phi) a.out_phi[idx] = 0.0;
+      if (a.out_p) a.out_p[idx] = 0.0;
+      if (a.out_u) { a.out_u[idx] = 0.0; a.out_u[G.N + idx] = 0.0; a.out_u[2 * G.N + idx] = 0.0; }
+    }
+    return;
+  }
+  const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
+  const Nbhd nb = make_nbhd(x, y, z, G);
+  R h[Q_H], g[Q_G];
+  load_pops<S, ODD>(a.h, a.g, G.N, idx, nb, walls, a.cd, h, g);
+  R Gx, Gy, Gz, lap;
+  stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
+  CellState<R> c;
+  prologue(h, g, Gx, Gy, Gz, lap, a.P, c);
+  if (MODE == MODE_MOMENTS) {
+    if (a.out_phi) a.out_phi[idx] = double(c.phi);
+    if (a.out_p) a.out_p[idx] = double(c.p);
+    if (a.out_u) {
+      a.out_u[idx] = double(c.ux);
+      a.out_u[G.N + idx] = double(c.uy);
+      a.out_u[2 * G.N + idx] = double(c.uz);
+    }
+    return;
+  }
+  collide_g<R, MRT>(g, c, a.P);
+  collide_h<R, MRT>(h, c, a.P);
+  store_pops<S, ODD>(a.h, a.g, G.N, idx, nb, walls, a.cd, h, g);
+}
+
+// Neighbour-is-wall bits for the populations of one cell, without LDS
+// (used by the light kernels: gather, readout, reductions).
+template <bool MASK>
+__device__ __forceinline__ unsigned wall_bits_direct(int x, int y, int z, const Geom& G,
+                                                     const unsigned char* __restrict__ mask) {
+  unsigned b = 0;
+#pragma unroll
+  for (int k = 1; k < 27; ++k) {
+    const Dir d = cg(k);
+    int X = x + d.x, Y = y + d.y, Z = z + d.z;
+    bool ok = wrap(X, G.nx, G.px) && wrap(Y, G.ny, G.py) && wrap(Z, G.nz, G.pz);
+    if (ok && MASK) ok = !mask[X + (long long)G.nx * (Y + (long long)G.ny * Z)];
+    if (!ok) b |= 1u << k;
+  }
+  return b;
+}
+
+template <typename S>
+struct LightArgs {
+  using R = typename Store<S>::R;
+  const S* h;
+  const S* g;
+  const unsigned char* mask;
+  Geom geo;
+  Codec<R> cd;
+  R* phi_out;          // gather target (compute precision)
+  double* out_h;       // natural-order FP64 populations
+  double* out_g;
+  double* out_phi64;   // FP64 phi
+  double* partials;    // [nblocks][5]
+};
+
+enum LightMode { LM_GATHER = 0, LM_READ_POPS = 1, LM_REDUCE = 2 };
+
+// phi gather (phi = sum h with the read rule of the next step), population
+// readout, or per-block FP64 sums.
+template <typename S, bool ODD, bool MASK, int LM>
+__global__ __launch_bounds__(256) void k_light(LightArgs<S> a) {
+  using R = typename Store<S>::R;
+  const Geom& G = a.geo;
+  const TileCoord t = tile_of_block(G);
+  const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y, z = t.z;
+  const bool in = x < G.nx && y < G.ny;
+  double acc[5] = {0, 0, 0, 0, 0};
+  if (in) {
+    const long long idx = x + (long long)G.nx * (y + (long long)G.ny * z);
+    const bool solid = MASK && a.mask[idx];
+    if (solid) {
+      if (LM == LM_GATHER) a.phi_out[idx] = R(0);
+      if (LM == LM_READ_POPS) {
+        for (int i = 0; i < Q_H; ++i) a.out_h[i * G.N + idx] = 0.0;
+        for (int i = 0; i < Q_G; ++i) a.out_g[i * G.N + idx] = 0.0;
+      }
+    } else {
+      const unsigned walls = ODD ? wall_bits_direct<MASK>(x, y, z, G, a.mask) : 0u;
+      const Nbhd nb = make_nbhd(x, y, z, G);
+      R h[Q_H], g[Q_G];
+      if (LM == LM_GATHER) {
+        using St = Store<S>;
+#pragma unroll
+        for (int i = 0; i < Q_H; ++i) {
+          long long ad = (long long)i * G.N + idx;
+          if (ODD) {
+            const Dir d = ch(i);
+            if (!(walls & (1u << nb27(-d.x, -d.y, -d.z))))
+              ad = (long long)opp(i) * G.N + nb.at(-d.x, -d.y, -d.z);
+          }
+          h[i] = St::ld(a.h + ad, a.cd.sh_h[i], a.cd.inv_scale_h);
+        }
+        const R s = sum_h(h);
+        a.phi_out[idx] = s;
+        if (a.out_phi64) a.out_phi64[idx] = double(s);
+      } else {
+        load_pops<S, ODD>(a.h, a.g, G.N, idx, nb, walls, a.cd, h, g);
+        if (LM == LM_READ_POPS) {
+#pragma unroll
+          for (int i = 0; i < Q_H; ++i) a.out_h[i * G.N + idx] = double(h[i]);
+#pragma unroll
+          for (int i = 0; i < Q_G; ++i) a.out_g[i * G.N + idx] = double(g[i]);
+        } else {
+          double s = 0;
+#pragma unroll
+          for (int i = 0; i < Q_H; ++i) s += double(h[i]);
+          acc[0] = s;
+#pragma unroll
+          for (int i = 0; i < Q_G; ++i) {
+            const Dir d = cg(i);
+            const double v = double(g[i]);
+            acc[1] += v;
+            acc[2] += d.x * v;
+            acc[3] += d.y * v;
+            acc[4] += d.z * v;
+          }
+        }
+      }
+    }
+  }
+  if (LM == LM_REDUCE) {
+    // wave64 butterfly, then the 4 waves of the block through LDS (fixed order)
+    __shared__ double red[4][5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double v = acc[k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      acc[k] = v;
+    }
+    const int tid = threadIdx.x + threadIdx.y * G.bx;
+    if ((tid & 63) == 0) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) red[tid >> 6][k] = acc[k];
+    }
+    __syncthreads();
+    if (tid < 5) {
+      a.partials[(long long)blockIdx.x * 5 + tid] =
+          ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    }
+  }
+}
+
+// Second reduction pass: one block sums nblocks x 5 partials in a fixed order.
+__global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict__ partials,
+                                                       unsigned nblocks, int ncomp,
+                                                       double* __restrict__ out) {
+  __shared__ double red[16][8];
+  const int tid = threadIdx.x;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (unsigned b = tid; b < nblocks; b += 1024)
+    for (int k = 0; k < ncomp; ++k) acc[k] += partials[(long long)b * ncomp + k];
+  for (int k = 0; k < ncomp; ++k) {
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    acc[k] = v;
+  }
+  if ((tid & 63) == 0)
+    for (int k = 0; k < ncomp; ++k) red[tid >> 6][k] = acc[k];
+  __syncthreads();
+  if (tid < ncomp) {
+    double s = 0;
+    for (int w = 0; w < 16; ++w) s += red[w][tid];
+    out[tid] = s;
+  }
+}
+
+template <typename S>
+struct InitArgs {
+  using R = typename Store<S>::R;
+  S* h;
+  S* g;
+  const unsigned char* mask;
+  const double* phi0;
+  const double* u0;      // may be null
+  const double* p0;      // may be null
+  Geom geo;
+  Codec<R> cd;
+};
+
+// Equilibrium initialisation in the natural layout (the even-step read rule).
+template <typename S, bool MASK>
+__global__ __launch_bounds__(256) void k_init(InitArgs<S> a) {
+  using R = typename Store<S>::R;
+  using St = Store<S>;
+  const Geom& G = a.geo;
+  const TileCoord t = tile_of_block(G);
+  const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y, z = t.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const long long idx = x + (long long)G.nx * (y + (long long)G.ny * z);
+  const bool solid = MASK && a.mask[idx];
+  const R phi = solid ? R(0) : R(a.phi0[idx]);
+  R ux = R(0), uy = R(0), uz = R(0), p = R(0);
+  if (!solid && a.u0) { ux = R(a.u0[idx]); uy = R(a.u0[G.N + idx]); uz = R(a.u0[2 * G.N + idx]); }
+  if (!solid && a.p0) p = R(a.p0[idx]);
+  const R base = R(1) - R(1.5) * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    const R cu = dot(ch(i), ux, uy, uz);
+    const R v = R(wh(i)) * phi * (base + cu * (R(3) + R(4.5) * cu));
+    St::st(a.h + (long long)i * G.N + idx, v, a.cd.sh_h[i], a.cd.scale_h);
+  }
+  const R baseg = p - R(1.5) * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    const R cu = dot(cg(i), ux, uy, uz);
+    const R v = R(wg(i)) * (baseg + cu * (R(3) + R(4.5) * cu));
+    St::st(a.g + (long long)i * G.N + idx, v, R(0), a.cd.scale_g);
+  }
+}
+
+// phi (compute precision) -> FP64
+template <typename R>
+__global__ __launch_bounds__(256) void k_phi_to_f64(const R* __restrict__ phi, long long N,
+                                                     double* __restrict__ out) {
+  const long long i = blockIdx.x * 256ll + threadIdx.x;
+  if (i < N) out[i] = double(phi[i]);
+}
+
+}  // namespace pflbm

@@ -1,0 +1,581 @@
+// C ABI of the coupled phase-field LBM step (see include/pflbm.h).
+//
+// Host side: argument checking, workspace carving, kernel dispatch over the
+// compile-time variants (storage type x collision x AA parity x mask), and
+// the adjoint bookkeeping.  Every launch goes to the context's stream; the
+// library never allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pflbm.h"
+#include "adjoint.hpp"
+#include "kernels.hpp"
+
+using namespace pflbm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+size_t store_size(int precision) { return precision == PFLBM_FP64 ? 8 : precision == PFLBM_FP32 ? 4 : 2; }
+size_t real_size(int precision) { return precision == PFLBM_FP64 ? 8 : 4; }
+
+bool desc_ok(const pflbm_desc* d) {
+  if (!d) return false;
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return false;
+  if (d->precision < 0 || d->precision > 2) return false;
+  if (d->collision < 0 || d->collision > 1) return false;
+  if (d->periodic > 7u) return false;
+  const long long N = (long long)d->nx * d->ny * d->nz;
+  if (N > (1ll << 31) - 1) return false;
+  return true;
+}
+
+struct Layout {
+  int bx, by, tiles_x, tiles_y;
+  unsigned nblocks;
+  long long N;
+  size_t off_h, off_g, off_phi[2], off_mask, off_part, off_red, total;
+  size_t bytes_h, bytes_g, bytes_phi;
+};
+
+Layout make_layout(const pflbm_desc* d) {
+  Layout L{};
+  L.bx = d->nx > 32 ? 64 : (d->nx > 16 ? 32 : 16);
+  L.by = 256 / L.bx;
+  L.tiles_x = (d->nx + L.bx - 1) / L.bx;
+  L.tiles_y = (d->ny + L.by - 1) / L.by;
+  L.nblocks = (unsigned)L.tiles_x * (unsigned)L.tiles_y * (unsigned)d->nz;
+  L.N = (long long)d->nx * d->ny * d->nz;
+  const size_t ss = store_size(d->precision), rs = real_size(d->precision);
+  L.bytes_h = (size_t)Q_H * L.N * ss;
+  L.bytes_g = (size_t)Q_G * L.N * ss;
+  L.bytes_phi = (size_t)L.N * rs;
+  size_t o = 0;
+  L.off_h = o; o = align_up(o + L.bytes_h);
+  L.off_g = o; o = align_up(o + L.bytes_g);
+  L.off_phi[0] = o; o = align_up(o + L.bytes_phi);
+  L.off_phi[1] = o; o = align_up(o + L.bytes_phi);
+  L.off_mask = o; if (d->has_mask) o = align_up(o + (size_t)L.N);
+  L.off_part = o; o = align_up(o + (size_t)L.nblocks * 8 * sizeof(double));
+  L.off_red = o; o = align_up(o + 8 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+struct AdjLayout {
+  size_t off_lh[2], off_lg[2], off_aphi[2], off_as, off_part, off_gsum, off_red, total;
+  size_t bytes_lh, bytes_lg, bytes_aphi, bytes_as;
+};
+
+AdjLayout make_adj_layout(const pflbm_desc* d, const Layout& L) {
+  AdjLayout A{};
+  const size_t rs = real_size(d->precision);
+  A.bytes_lh = (size_t)Q_H * L.N * rs;
+  A.bytes_lg = (size_t)Q_G * L.N * rs;
+  A.bytes_aphi = (size_t)L.N * rs;
+  A.bytes_as = (size_t)4 * L.N * rs;
+  size_t o = 0;
+  for (int k = 0; k < 2; ++k) { A.off_lh[k] = o; o = align_up(o + A.bytes_lh); }
+  for (int k = 0; k < 2; ++k) { A.off_lg[k] = o; o = align_up(o + A.bytes_lg); }
+  for (int k = 0; k < 2; ++k) { A.off_aphi[k] = o; o = align_up(o + A.bytes_aphi); }
+  A.off_as = o; o = align_up(o + A.bytes_as);
+  A.off_part = o; o = align_up(o + (size_t)L.nblocks * 2 * sizeof(double));
+  A.off_gsum = o; o = align_up(o + (size_t)L.nblocks * 2 * sizeof(double));
+  A.off_red = o; o = align_up(o + 8 * sizeof(double));
+  A.total = o;
+  return A;
+}
+
+double fp16_round(double v) {
+  if (v == 0.0) return 0.0;
+  int e;
+  const double m = std::frexp(v, &e);            // v = m 2^e, 0.5 <= |m| < 1
+  return std::ldexp(std::nearbyint(std::ldexp(m, 11)), e - 11);
+}
+
+}  // namespace
+
+struct pflbm_ctx {
+  pflbm_desc d;
+  pflbm_params p;
+  hipStream_t stream;
+  Layout L;
+  char* ws;
+  int cur = 0;
+  int64_t steps = 0;
+  bool initialised = false;
+  bool mask_set = false;
+  // adjoint
+  char* adj = nullptr;
+  AdjLayout A{};
+  int acur = 0;
+  std::string err;
+};
+
+namespace {
+
+pflbm_status fail(pflbm_ctx* c, pflbm_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+pflbm_status check_hip(pflbm_ctx* c, hipError_t e, const char* where) {
+  if (e == hipSuccess) return PFLBM_OK;
+  return fail(c, PFLBM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+Geom make_geom(const pflbm_ctx* c) {
+  Geom G;
+  G.nx = c->d.nx; G.ny = c->d.ny; G.nz = c->d.nz;
+  G.px = (c->d.periodic >> 0) & 1; G.py = (c->d.periodic >> 1) & 1; G.pz = (c->d.periodic >> 2) & 1;
+  G.bx = c->L.bx; G.by = c->L.by;
+  G.tiles_x = c->L.tiles_x; G.tiles_y = c->L.tiles_y;
+  G.nblocks = c->L.nblocks;
+  G.N = c->L.N;
+  return G;
+}
+
+template <typename R>
+Phys<R> make_phys(const pflbm_params& p) {
+  Phys<R> P;
+  const bool inf_xi = std::isinf(p.xi);
+  P.tau_L = R(p.tau_L);
+  P.dtau = R(p.tau_H - p.tau_L);
+  P.rho_L = R(p.rho_L);
+  P.drho = R(p.rho_H - p.rho_L);
+  P.theta_k = inf_xi ? R(0) : R(4.0 / p.xi);
+  P.beta4 = inf_xi ? R(0) : R(48.0 * p.sigma / p.xi);
+  P.kappa = inf_xi ? R(0) : R(1.5 * p.sigma * p.xi);
+  P.gx = R(p.g[0]); P.gy = R(p.g[1]); P.gz = R(p.g[2]);
+  P.omega_phi = R(1.0 / (3.0 * p.mobility + 0.5));
+  P.s_high = R(p.s_high);
+  P.eps2 = R(1e-24);
+  return P;
+}
+
+template <typename R>
+Codec<R> make_codec(const pflbm_ctx* c) {
+  Codec<R> cd;
+  const bool f16 = c->d.precision == PFLBM_FP32_FP16S;
+  for (int i = 0; i < Q_H; ++i) cd.sh_h[i] = f16 ? R(fp16_round(wh(i))) : R(0);
+  const double kh = f16 ? c->p.fp16_scale_log2[0] : 0.0, kg = f16 ? c->p.fp16_scale_log2[1] : 0.0;
+  cd.scale_h = R(std::ldexp(1.0, (int)kh));
+  cd.inv_scale_h = R(std::ldexp(1.0, -(int)kh));
+  cd.scale_g = R(std::ldexp(1.0, (int)kg));
+  cd.inv_scale_g = R(std::ldexp(1.0, -(int)kg));
+  return cd;
+}
+
+template <typename S> S* pop_h(pflbm_ctx* c) { return reinterpret_cast<S*>(c->ws + c->L.off_h); }
+template <typename S> S* pop_g(pflbm_ctx* c) { return reinterpret_cast<S*>(c->ws + c->L.off_g); }
+template <typename R> R* phi_buf(pflbm_ctx* c, int k) { return reinterpret_cast<R*>(c->ws + c->L.off_phi[k]); }
+unsigned char* mask_ptr(pflbm_ctx* c) {
+  return c->d.has_mask ? reinterpret_cast<unsigned char*>(c->ws + c->L.off_mask) : nullptr;
+}
+
+// ---- launch helpers ----------------------------------------------------------
+template <typename S, bool MRT, bool ODD, int MODE>
+void launch_cell_m(pflbm_ctx* c, const CellArgs<S>& a) {
+  using R = typename Store<S>::R;
+  const size_t sm = (size_t)(c->L.bx + 2) * (c->L.by + 2) * 3 * sizeof(R);
+  const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
+  if (c->d.has_mask)
+    hipLaunchKernelGGL((k_cell<S, MRT, ODD, true, MODE>), grd, blk, sm, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_cell<S, MRT, ODD, false, MODE>), grd, blk, sm, c->stream, a);
+}
+
+template <typename S, int MODE>
+void launch_cell(pflbm_ctx* c, const CellArgs<S>& a, bool odd) {
+  const bool mrt = c->d.collision == PFLBM_MRT;
+  if (mrt) {
+    if (odd) launch_cell_m<S, true, true, MODE>(c, a); else launch_cell_m<S, true, false, MODE>(c, a);
+  } else {
+    if (odd) launch_cell_m<S, false, true, MODE>(c, a); else launch_cell_m<S, false, false, MODE>(c, a);
+  }
+}
+
+template <typename S, int LM>
+void launch_light(pflbm_ctx* c, const LightArgs<S>& a, bool odd) {
+  const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
+  const bool m = c->d.has_mask;
+  if (odd) {
+    if (m) hipLaunchKernelGGL((k_light<S, true, true, LM>), grd, blk, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_light<S, true, false, LM>), grd, blk, 0, c->stream, a);
+  } else {
+    if (m) hipLaunchKernelGGL((k_light<S, false, true, LM>), grd, blk, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_light<S, false, false, LM>), grd, blk, 0, c->stream, a);
+  }
+}
+
+template <typename S>
+CellArgs<S> cell_args(pflbm_ctx* c) {
+  using R = typename Store<S>::R;
+  CellArgs<S> a;
+  a.h = pop_h<S>(c);
+  a.g = pop_g<S>(c);
+  a.phi = phi_buf<R>(c, c->cur);
+  a.mask = mask_ptr(c);
+  a.geo = make_geom(c);
+  a.P = make_phys<R>(c->p);
+  a.cd = make_codec<R>(c);
+  a.out_phi = a.out_u = a.out_p = nullptr;
+  return a;
+}
+
+template <typename S>
+LightArgs<S> light_args(pflbm_ctx* c) {
+  using R = typename Store<S>::R;
+  LightArgs<S> a;
+  a.h = pop_h<S>(c);
+  a.g = pop_g<S>(c);
+  a.mask = mask_ptr(c);
+  a.geo = make_geom(c);
+  a.cd = make_codec<R>(c);
+  a.phi_out = nullptr;
+  a.out_h = a.out_g = a.out_phi64 = nullptr;
+  a.partials = nullptr;
+  return a;
+}
+
+// phi^n = sum h with the read rule of the step the counter points at
+template <typename S>
+void gather_phi(pflbm_ctx* c, int target) {
+  using R = typename Store<S>::R;
+  LightArgs<S> a = light_args<S>(c);
+  a.phi_out = phi_buf<R>(c, target);
+  launch_light<S, LM_GATHER>(c, a, c->steps & 1);
+}
+
+template <typename S>
+pflbm_status do_steps(pflbm_ctx* c, int64_t n) {
+  for (int64_t s = 0; s < n; ++s) {
+    CellArgs<S> a = cell_args<S>(c);
+    launch_cell<S, MODE_STEP>(c, a, c->steps & 1);
+    c->steps += 1;
+    gather_phi<S>(c, c->cur ^ 1);
+    c->cur ^= 1;
+  }
+  return check_hip(c, hipGetLastError(), "pflbm_step");
+}
+
+template <typename S>
+pflbm_status do_profile(pflbm_ctx* c, int64_t n, double* out_ms) {
+  // events around every launch, read back once at the end (no per-step sync)
+  std::vector<hipEvent_t> ev((size_t)(2 * n + 1));
+  for (auto& e : ev)
+    if (pflbm_status s = check_hip(c, hipEventCreate(&e), "pflbm_profile_step event")) return s;
+  hipEventRecord(ev[0], c->stream);
+  for (int64_t s = 0; s < n; ++s) {
+    CellArgs<S> a = cell_args<S>(c);
+    launch_cell<S, MODE_STEP>(c, a, c->steps & 1);
+    hipEventRecord(ev[2 * s + 1], c->stream);
+    c->steps += 1;
+    gather_phi<S>(c, c->cur ^ 1);
+    c->cur ^= 1;
+    hipEventRecord(ev[2 * s + 2], c->stream);
+  }
+  pflbm_status st = check_hip(c, hipEventSynchronize(ev[2 * n]), "pflbm_profile_step");
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t s = 0; s < n && !st; ++s) {
+    float t0 = 0.f, t1 = 0.f;
+    hipEventElapsedTime(&t0, ev[2 * s], ev[2 * s + 1]);
+    hipEventElapsedTime(&t1, ev[2 * s + 1], ev[2 * s + 2]);
+    acc[0] += t0;
+    acc[1] += t1;
+  }
+  if (!st && n > 0) {
+    float t = 0.f;
+    hipEventElapsedTime(&t, ev[0], ev[2 * n]);
+    acc[2] = t;
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  for (int k = 0; k < 3; ++k) out_ms[k] = acc[k];
+  if (st) return st;
+  return check_hip(c, hipGetLastError(), "pflbm_profile_step");
+}
+
+template <typename S>
+pflbm_status do_init(pflbm_ctx* c, const double* phi0, const double* u0, const double* p0) {
+  using R = typename Store<S>::R;
+  InitArgs<S> a;
+  a.h = pop_h<S>(c);
+  a.g = pop_g<S>(c);
+  a.mask = mask_ptr(c);
+  a.phi0 = phi0;
+  a.u0 = u0;
+  a.p0 = p0;
+  a.geo = make_geom(c);
+  a.cd = make_codec<R>(c);
+  const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
+  if (c->d.has_mask) hipLaunchKernelGGL((k_init<S, true>), grd, blk, 0, c->stream, a);
+  else hipLaunchKernelGGL((k_init<S, false>), grd, blk, 0, c->stream, a);
+  c->steps = 0;
+  c->cur = 0;
+  gather_phi<S>(c, 0);
+  return check_hip(c, hipGetLastError(), "pflbm_init_equilibrium");
+}
+
+template <typename S>
+pflbm_status do_moments(pflbm_ctx* c, double* phi, double* u, double* p) {
+  CellArgs<S> a = cell_args<S>(c);
+  a.out_phi = phi;
+  a.out_u = u;
+  a.out_p = p;
+  launch_cell<S, MODE_MOMENTS>(c, a, c->steps & 1);
+  return check_hip(c, hipGetLastError(), "pflbm_read_moments");
+}
+
+template <typename S>
+pflbm_status do_read_pops(pflbm_ctx* c, double* h, double* g) {
+  LightArgs<S> a = light_args<S>(c);
+  a.out_h = h;
+  a.out_g = g;
+  launch_light<S, LM_READ_POPS>(c, a, c->steps & 1);
+  return check_hip(c, hipGetLastError(), "pflbm_read_populations");
+}
+
+template <typename S>
+pflbm_status do_reduce(pflbm_ctx* c, double* out_host) {
+  LightArgs<S> a = light_args<S>(c);
+  double* part = reinterpret_cast<double*>(c->ws + c->L.off_part);
+  double* red = reinterpret_cast<double*>(c->ws + c->L.off_red);
+  a.partials = part;
+  launch_light<S, LM_REDUCE>(c, a, c->steps & 1);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->stream, part, c->L.nblocks, 5, red);
+  pflbm_status s = check_hip(c, hipGetLastError(), "pflbm_reduce launch");
+  if (s) return s;
+  s = check_hip(c, hipMemcpyAsync(out_host, red, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                "pflbm_reduce copy");
+  if (s) return s;
+  s = check_hip(c, hipStreamSynchronize(c->stream), "pflbm_reduce sync");
+  if (s) return s;
+  for (int k = 0; k < 5; ++k)
+    if (!std::isfinite(out_host[k])) return fail(c, PFLBM_ERR_UNSTABLE, "non-finite reduction");
+  return PFLBM_OK;
+}
+
+#define DISPATCH(c, fn, ...)                                     \
+  do {                                                           \
+    switch ((c)->d.precision) {                                  \
+      case PFLBM_FP64: return fn<double>(__VA_ARGS__);           \
+      case PFLBM_FP32: return fn<float>(__VA_ARGS__);            \
+      default: return fn<_Float16>(__VA_ARGS__);                 \
+    }                                                            \
+  } while (0)
+
+pflbm_status params_ok(const pflbm_params* p, std::string& why) {
+  if (!p) { why = "params is NULL"; return PFLBM_ERR_ARG; }
+  auto bad = [&](bool cond, const char* m) { if (cond) why = m; return cond; };
+  if (bad(!(p->tau_H > 0.5) || !(p->tau_L > 0.5), "tau must be > 1/2")) return PFLBM_ERR_ARG;
+  if (bad(!(p->mobility > 0) || !std::isfinite(p->mobility), "mobility must be > 0")) return PFLBM_ERR_ARG;
+  if (bad(!(p->xi > 0), "xi must be > 0")) return PFLBM_ERR_ARG;
+  if (bad(!(p->sigma >= 0) || !std::isfinite(p->sigma), "sigma must be >= 0")) return PFLBM_ERR_ARG;
+  if (bad(!(p->rho_H > 0) || !(p->rho_L > 0), "densities must be > 0")) return PFLBM_ERR_ARG;
+  if (bad(!(p->s_high > 0 && p->s_high < 2), "s_high must lie in (0, 2)")) return PFLBM_ERR_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (bad(!std::isfinite(p->g[k]), "g must be finite")) return PFLBM_ERR_ARG;
+  for (int k = 0; k < 2; ++k) {
+    const double v = p->fp16_scale_log2[k];
+    if (bad(!(std::fabs(v) <= 24) || v != std::floor(v), "fp16_scale_log2 must be integers in [-24, 24]"))
+      return PFLBM_ERR_ARG;
+  }
+  return PFLBM_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+size_t pflbm_workspace_bytes(const pflbm_desc* desc) {
+  if (!desc_ok(desc)) return 0;
+  return make_layout(desc).total;
+}
+
+pflbm_status pflbm_create(const pflbm_desc* desc, void* d_workspace, size_t bytes,
+                          void* hip_stream, pflbm_ctx** out) {
+  if (!out) return PFLBM_ERR_ARG;
+  *out = nullptr;
+  if (!desc_ok(desc) || !d_workspace) return PFLBM_ERR_ARG;
+  const Layout L = make_layout(desc);
+  if (bytes < L.total || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0) return PFLBM_ERR_ARG;
+  pflbm_ctx* c = new (std::nothrow) pflbm_ctx();
+  if (!c) return PFLBM_ERR_ARG;
+  c->d = *desc;
+  c->L = L;
+  c->ws = static_cast<char*>(d_workspace);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  pflbm_params p{};
+  p.tau_H = p.tau_L = 0.53;
+  p.mobility = 0.02;
+  p.xi = 4.0;
+  p.sigma = 1e-4;
+  p.rho_H = 1.0;
+  p.rho_L = 1e-3;
+  p.s_high = 1.0;
+  p.fp16_scale_log2[0] = 8;
+  p.fp16_scale_log2[1] = 12;
+  c->p = p;
+  *out = c;
+  return PFLBM_OK;
+}
+
+pflbm_status pflbm_destroy(pflbm_ctx* ctx) {
+  if (!ctx) return PFLBM_ERR_ARG;
+  delete ctx;
+  return PFLBM_OK;
+}
+
+pflbm_status pflbm_set_params(pflbm_ctx* c, const pflbm_params* p) {
+  if (!c) return PFLBM_ERR_ARG;
+  std::string why;
+  if (pflbm_status s = params_ok(p, why)) return fail(c, s, why);
+  c->p = *p;
+  return PFLBM_OK;
+}
+
+pflbm_status pflbm_set_mask(pflbm_ctx* c, const uint8_t* d_solid) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!c->d.has_mask) return fail(c, PFLBM_ERR_STATE, "context created without a mask");
+  if (!d_solid) return fail(c, PFLBM_ERR_ARG, "mask pointer is NULL");
+  pflbm_status s = check_hip(c, hipMemcpyAsync(mask_ptr(c), d_solid, (size_t)c->L.N,
+                                               hipMemcpyDeviceToDevice, c->stream), "pflbm_set_mask");
+  if (!s) c->mask_set = true;
+  return s;
+}
+
+pflbm_status pflbm_init_equilibrium(pflbm_ctx* c, const double* phi0, const double* u0,
+                                    const double* p0) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!phi0) return fail(c, PFLBM_ERR_ARG, "phi0 is NULL");
+  if (c->d.has_mask && !c->mask_set) return fail(c, PFLBM_ERR_STATE, "mask not set");
+  c->initialised = true;
+  DISPATCH(c, do_init, c, phi0, u0, p0);
+}
+
+pflbm_status pflbm_step(pflbm_ctx* c, int64_t n) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (n < 0) return fail(c, PFLBM_ERR_ARG, "negative step count");
+  if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
+  DISPATCH(c, do_steps, c, n);
+}
+
+pflbm_status pflbm_profile_step(pflbm_ctx* c, int64_t n, double* out_ms) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (n < 0 || !out_ms) return fail(c, PFLBM_ERR_ARG, "bad step count or output");
+  if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
+  DISPATCH(c, do_profile, c, n, out_ms);
+}
+
+pflbm_status pflbm_read_moments(pflbm_ctx* c, double* phi, double* u, double* p) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
+  DISPATCH(c, do_moments, c, phi, u, p);
+}
+
+pflbm_status pflbm_read_phi(pflbm_ctx* c, double* d_phi) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!d_phi) return fail(c, PFLBM_ERR_ARG, "output is NULL");
+  if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
+  const unsigned nb = (unsigned)((c->L.N + 255) / 256);
+  if (c->d.precision == PFLBM_FP64)
+    hipLaunchKernelGGL(k_phi_to_f64<double>, dim3(nb), dim3(256), 0, c->stream,
+                       phi_buf<double>(c, c->cur), c->L.N, d_phi);
+  else
+    hipLaunchKernelGGL(k_phi_to_f64<float>, dim3(nb), dim3(256), 0, c->stream,
+                       phi_buf<float>(c, c->cur), c->L.N, d_phi);
+  return check_hip(c, hipGetLastError(), "pflbm_read_phi");
+}
+
+pflbm_status pflbm_read_populations(pflbm_ctx* c, double* h, double* g) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!h || !g) return fail(c, PFLBM_ERR_ARG, "output is NULL");
+  if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
+  DISPATCH(c, do_read_pops, c, h, g);
+}
+
+pflbm_status pflbm_reduce(pflbm_ctx* c, double out_host[5]) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!out_host) return fail(c, PFLBM_ERR_ARG, "output is NULL");
+  if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
+  DISPATCH(c, do_reduce, c, out_host);
+}
+
+size_t pflbm_state_bytes(const pflbm_ctx* c) {
+  if (!c) return 0;
+  return c->L.bytes_h + c->L.bytes_g + c->L.bytes_phi;
+}
+
+pflbm_status pflbm_save_state(pflbm_ctx* c, void* dst) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!dst) return fail(c, PFLBM_ERR_ARG, "destination is NULL");
+  if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
+  char* o = static_cast<char*>(dst);
+  hipError_t e = hipMemcpyAsync(o, c->ws + c->L.off_h, c->L.bytes_h, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o + c->L.bytes_h, c->ws + c->L.off_g, c->L.bytes_g, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o + c->L.bytes_h + c->L.bytes_g, c->ws + c->L.off_phi[c->cur], c->L.bytes_phi,
+                       hipMemcpyDeviceToDevice, c->stream);
+  return check_hip(c, e, "pflbm_save_state");
+}
+
+pflbm_status pflbm_load_state(pflbm_ctx* c, const void* src, int64_t step_count) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!src || step_count < 0) return fail(c, PFLBM_ERR_ARG, "bad source or step count");
+  if (c->d.has_mask && !c->mask_set) return fail(c, PFLBM_ERR_STATE, "mask not set");
+  const char* o = static_cast<const char*>(src);
+  hipError_t e = hipMemcpyAsync(c->ws + c->L.off_h, o, c->L.bytes_h, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + c->L.off_g, o + c->L.bytes_h, c->L.bytes_g, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + c->L.off_phi[0], o + c->L.bytes_h + c->L.bytes_g, c->L.bytes_phi,
+                       hipMemcpyDeviceToDevice, c->stream);
+  c->cur = 0;
+  c->steps = step_count;
+  c->initialised = true;
+  return check_hip(c, e, "pflbm_load_state");
+}
+
+int64_t pflbm_step_count(const pflbm_ctx* c) { return c ? c->steps : -1; }
+
+pflbm_status pflbm_sync(pflbm_ctx* c) {
+  if (!c) return PFLBM_ERR_ARG;
+  return check_hip(c, hipStreamSynchronize(c->stream), "pflbm_sync");
+}
+
+pflbm_status pflbm_lattice(int32_t q, int32_t* c_out, double* w_out) {
+  if (q != 15 && q != 27) return PFLBM_ERR_ARG;
+  for (int i = 0; i < q; ++i) {
+    const Dir d = q == 15 ? ch(i) : cg(i);
+    if (c_out) { c_out[3 * i] = d.x; c_out[3 * i + 1] = d.y; c_out[3 * i + 2] = d.z; }
+    if (w_out) w_out[i] = q == 15 ? wh(i) : wg(i);
+  }
+  return PFLBM_OK;
+}
+
+const char* pflbm_status_string(pflbm_status s) {
+  switch (s) {
+    case PFLBM_OK: return "ok";
+    case PFLBM_ERR_ARG: return "invalid argument";
+    case PFLBM_ERR_STATE: return "invalid state";
+    case PFLBM_ERR_HIP: return "HIP error";
+    case PFLBM_ERR_UNSTABLE: return "unstable (non-finite reduction)";
+    case PFLBM_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* pflbm_last_error(const pflbm_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+}  // extern "C"
+
+#include "adjoint_api.inc"

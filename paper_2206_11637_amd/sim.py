@@ -1,0 +1,200 @@
+"""Simulation: a context of the HIP library plus the torch buffers it lives in."""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Desc, Params, check, load
+
+
+def lattice(q: int):
+    """(c [q,3] int array, w [q] float array) in the library's velocity order."""
+    lib = load()
+    c = (C.c_int32 * (3 * q))()
+    w = (C.c_double * q)()
+    check(lib.pflbm_lattice(q, c, w), None, "pflbm_lattice")
+    return np.array(c[:], dtype=np.int64).reshape(q, 3), np.array(w[:])
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _params_struct(p) -> Params:
+    get = (lambda k: p[k]) if isinstance(p, dict) else (lambda k: getattr(p, k))
+    s = Params()
+    s.tau_H, s.tau_L = get("tau_H"), get("tau_L")
+    s.mobility, s.xi, s.sigma = get("mobility"), get("xi"), get("sigma")
+    s.rho_H, s.rho_L = get("rho_H"), get("rho_L")
+    for k, v in enumerate(get("g")):
+        s.g[k] = v
+    s.s_high = get("s_high")
+    for k, v in enumerate(get("fp16_scale_log2")):
+        s.fp16_scale_log2[k] = v
+    return s
+
+
+class Simulation:
+    """One lattice on one GPU.
+
+    Fields handed in or out are float64 torch tensors on the context's device
+    with shapes [nz, ny, nx] (scalars) and [3, nz, ny, nx] (vectors).
+    """
+
+    def __init__(self, nx: int, ny: int, nz: int, periodic=(True, False, True),
+                 precision: str = "fp32", collision: str = "mrt", solid=None, params=None,
+                 device: str = "cuda:0"):
+        self.lib = load()
+        self.device = torch.device(device)
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+        self.precision = precision
+        pbits = int(bool(periodic[0])) | (int(bool(periodic[1])) << 1) | (int(bool(periodic[2])) << 2)
+        self.desc = Desc(nx, ny, nz, pbits, _lib.PRECISIONS[precision],
+                         _lib.COLLISIONS[collision], int(solid is not None))
+        nbytes = self.lib.pflbm_workspace_bytes(C.byref(self.desc))
+        if nbytes == 0:
+            raise ValueError(f"invalid lattice description {nx}x{ny}x{nz}")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        check(self.lib.pflbm_create(C.byref(self.desc), _ptr(self.workspace), nbytes,
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(ctx)),
+              None, "pflbm_create")
+        self.ctx = ctx
+        self._adj_ws = None
+        if params is not None:
+            self.set_params(params)
+        if solid is not None:
+            m = torch.as_tensor(np.asarray(solid, dtype=np.uint8)).reshape(-1).to(self.device)
+            self._mask = m
+            check(self.lib.pflbm_set_mask(self.ctx, _ptr(m)), self.ctx, "pflbm_set_mask")
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.pflbm_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # ---- helpers -------------------------------------------------------------
+    def _f64(self, a, shape) -> torch.Tensor:
+        t = torch.as_tensor(a, dtype=torch.float64).to(self.device).reshape(shape).contiguous()
+        return t
+
+    # ---- forward -------------------------------------------------------------
+    def set_params(self, p) -> None:
+        s = _params_struct(p)
+        check(self.lib.pflbm_set_params(self.ctx, C.byref(s)), self.ctx, "pflbm_set_params")
+
+    def init_equilibrium(self, phi0, u0=None, pstar0=None) -> None:
+        phi = self._f64(phi0, (-1,))
+        u = None if u0 is None else self._f64(u0, (-1,))
+        p = None if pstar0 is None else self._f64(pstar0, (-1,))
+        self._init_keep = (phi, u, p)   # alive until the kernels have read them
+        check(self.lib.pflbm_init_equilibrium(self.ctx, _ptr(phi), _ptr(u), _ptr(p)), self.ctx,
+              "pflbm_init_equilibrium")
+
+    def step(self, n: int = 1) -> None:
+        check(self.lib.pflbm_step(self.ctx, int(n)), self.ctx, "pflbm_step")
+
+    @property
+    def step_count(self) -> int:
+        return int(self.lib.pflbm_step_count(self.ctx))
+
+    def moments(self):
+        nz, ny, nx = self.shape
+        phi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        p = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        check(self.lib.pflbm_read_moments(self.ctx, _ptr(phi), _ptr(u), _ptr(p)), self.ctx,
+              "pflbm_read_moments")
+        return phi, u, p
+
+    def phi(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        check(self.lib.pflbm_read_phi(self.ctx, _ptr(out)), self.ctx, "pflbm_read_phi")
+        return out
+
+    def populations(self):
+        h = torch.empty((15, self.N), dtype=torch.float64, device=self.device)
+        g = torch.empty((27, self.N), dtype=torch.float64, device=self.device)
+        check(self.lib.pflbm_read_populations(self.ctx, _ptr(h), _ptr(g)), self.ctx,
+              "pflbm_read_populations")
+        return h, g
+
+    def reduce(self) -> np.ndarray:
+        out = (C.c_double * 5)()
+        check(self.lib.pflbm_reduce(self.ctx, out), self.ctx, "pflbm_reduce")
+        return np.array(out[:])
+
+    def state_bytes(self) -> int:
+        return int(self.lib.pflbm_state_bytes(self.ctx))
+
+    def save_state(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        check(self.lib.pflbm_save_state(self.ctx, _ptr(out)), self.ctx, "pflbm_save_state")
+        return out
+
+    def load_state(self, buf: torch.Tensor, step_count: int) -> None:
+        check(self.lib.pflbm_load_state(self.ctx, _ptr(buf), int(step_count)), self.ctx,
+              "pflbm_load_state")
+
+    def profile_step(self, n: int):
+        """Steps n times under HIP events; returns milliseconds
+        (collide-stream kernels summed, phi-update kernels summed, total)."""
+        out = (C.c_double * 3)()
+        check(self.lib.pflbm_profile_step(self.ctx, int(n), out), self.ctx, "pflbm_profile_step")
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def sync(self) -> None:
+        check(self.lib.pflbm_sync(self.ctx), self.ctx, "pflbm_sync")
+
+    # ---- reverse mode ----------------------------------------------------------
+    def adjoint_attach(self) -> None:
+        n = self.lib.pflbm_adjoint_workspace_bytes(C.byref(self.desc))
+        if self._adj_ws is None:
+            self._adj_ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        check(self.lib.pflbm_adjoint_attach(self.ctx, _ptr(self._adj_ws), n), self.ctx,
+              "pflbm_adjoint_attach")
+
+    def adjoint_reset(self) -> None:
+        check(self.lib.pflbm_adjoint_reset(self.ctx), self.ctx, "pflbm_adjoint_reset")
+
+    def adjoint_inject_phi(self, dl_dphi: torch.Tensor) -> None:
+        t = self._f64(dl_dphi, (-1,))
+        self._inj_keep = t
+        check(self.lib.pflbm_adjoint_inject_phi(self.ctx, _ptr(t)), self.ctx,
+              "pflbm_adjoint_inject_phi")
+
+    def adjoint_step(self, state_n: torch.Tensor, n: int) -> None:
+        check(self.lib.pflbm_adjoint_step(self.ctx, _ptr(state_n), int(n)), self.ctx,
+              "pflbm_adjoint_step")
+
+    def adjoint_init(self, u0=None) -> torch.Tensor:
+        u = None if u0 is None else self._f64(u0, (-1,))
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        check(self.lib.pflbm_adjoint_init(self.ctx, _ptr(u), _ptr(out)), self.ctx,
+              "pflbm_adjoint_init")
+        return out
+
+    def adjoint_grads(self):
+        out = (C.c_double * 2)()
+        check(self.lib.pflbm_adjoint_grads(self.ctx, out), self.ctx, "pflbm_adjoint_grads")
+        return float(out[0]), float(out[1])
+
+
+def from_workload(wl, precision="fp32", collision="mrt", device="cuda:0", params=None) -> Simulation:
+    """Simulation for a workloads.Workload, initialised at equilibrium."""
+    sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, precision, collision, wl.solid,
+                     params if params is not None else wl.params, device)
+    sim.init_equilibrium(wl.phi0, wl.u0, wl.pstar0)
+    return sim

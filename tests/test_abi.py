@@ -1,0 +1,175 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+validates descriptions, and its host-side tables and addressing are right.
+No compute call is made here (no GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pflbm.h")
+
+
+def _lib():
+    from paper_2206_11637_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libpflbm.so not built")
+    return L, L.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pflbm_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    L, lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares exactly the header's functions
+    assert sorted(L.SIGNATURES) == names
+
+
+def test_workspace_sizes_and_invalid_descriptions():
+    L, lib = _lib()
+    d = L.Desc(32, 32, 32, 5, 0, 1, 0)
+    n64 = lib.pflbm_workspace_bytes(C.byref(d))
+    N = 32 ** 3
+    assert n64 >= (42 * 8 + 2 * 8) * N
+    d32 = L.Desc(32, 32, 32, 5, 1, 1, 0)
+    d16 = L.Desc(32, 32, 32, 5, 2, 1, 1)
+    assert lib.pflbm_workspace_bytes(C.byref(d32)) >= (42 * 4 + 8) * N
+    assert lib.pflbm_workspace_bytes(C.byref(d16)) >= (42 * 2 + 8 + 1) * N
+    for bad in (L.Desc(0, 4, 4, 0, 0, 0, 0), L.Desc(4, 4, 4, 9, 0, 0, 0),
+                L.Desc(4, 4, 4, 0, 3, 0, 0), L.Desc(4, 4, 4, 0, 0, 2, 0)):
+        assert lib.pflbm_workspace_bytes(C.byref(bad)) == 0
+    ctx = C.c_void_p()
+    assert lib.pflbm_create(C.byref(L.Desc(0, 4, 4, 0, 0, 0, 0)), C.c_void_p(256), 1 << 20,
+                            None, C.byref(ctx)) == L.PFLBM_ERR_ARG
+    assert lib.pflbm_create(C.byref(d), C.c_void_p(256), 10, None, C.byref(ctx)) == L.PFLBM_ERR_ARG
+    assert lib.pflbm_status_string(L.PFLBM_ERR_UNSTABLE).decode().startswith("unstable")
+
+
+def test_parameter_validation_without_a_gpu():
+    """set_params checks arguments on the host (the workspace pointer is never
+    dereferenced by create/set_params/destroy)."""
+    L, lib = _lib()
+    d = L.Desc(8, 8, 8, 7, 1, 1, 0)
+    n = lib.pflbm_workspace_bytes(C.byref(d))
+    ctx = C.c_void_p()
+    assert lib.pflbm_create(C.byref(d), C.c_void_p(4096), n, None, C.byref(ctx)) == 0
+    import workloads as W
+    from paper_2206_11637_amd.sim import _params_struct
+    good = _params_struct(W.Params())
+    assert lib.pflbm_set_params(ctx, C.byref(good)) == 0
+    for field, val in (("tau_H", 0.5), ("mobility", 0.0), ("xi", -1.0), ("sigma", -1e-4),
+                       ("rho_L", 0.0), ("s_high", 2.0)):
+        p = _params_struct(W.Params())
+        setattr(p, field, val)
+        assert lib.pflbm_set_params(ctx, C.byref(p)) == L.PFLBM_ERR_ARG, field
+        assert len(lib.pflbm_last_error(ctx)) > 0
+    p = _params_struct(W.Params())
+    p.fp16_scale_log2[0] = 3.5
+    assert lib.pflbm_set_params(ctx, C.byref(p)) == L.PFLBM_ERR_ARG
+    # stepping before init is a state error, not a crash
+    assert lib.pflbm_step(ctx, 1) == L.PFLBM_ERR_STATE
+    assert lib.pflbm_destroy(ctx) == 0
+
+
+def test_library_velocity_sets_match_the_oracle_lattices():
+    from oracle import lattice as OL
+    from paper_2206_11637_amd.sim import lattice
+    for q, lat in ((15, OL.D3Q15), (27, OL.D3Q27)):
+        c, w = lattice(q)
+        assert sorted(map(tuple, c)) == sorted(map(tuple, lat.c_np))
+        wo = {tuple(v): lat.w_np[i] for i, v in enumerate(lat.c_np)}
+        for i in range(q):
+            assert abs(w[i] - wo[tuple(c[i])]) < 1e-16
+        # opposite pairs are adjacent (the kernels rely on it)
+        for i in range(1, q, 2):
+            assert (c[i] == -c[i + 1]).all()
+
+
+def xcd_remap(b, nb):
+    """Host restatement of the kernels' block renumbering (checked to be a bijection)."""
+    q, r, x, k = nb >> 3, nb & 7, b & 7, b >> 3
+    return x * (q + 1) + k if x < r else r * (q + 1) + (x - r) * q + k
+
+
+@pytest.mark.parametrize("nb", [1, 7, 8, 9, 64, 1001, 65536 + 5])
+def test_xcd_remap_is_a_bijection_with_contiguous_ranges(nb):
+    b = np.arange(nb)
+    out = np.array([xcd_remap(int(v), nb) for v in b])
+    assert sorted(out.tolist()) == list(range(nb))
+    for x in range(8):
+        sel = np.sort(out[b % 8 == x])
+        if len(sel):
+            assert (np.diff(sel) == 1).all()
+
+
+def _aa_maps(nx, ny, nz, periodic, solid, c, odd):
+    """Slots (population, cell) read and written by each fluid cell under the
+    in-place AA rules, as the kernels compute them."""
+    q = len(c)
+    opp = [0] + [i + 1 if i % 2 else i - 1 for i in range(1, q)]
+    N = nx * ny * nz
+
+    def nb(x, y, z, d):
+        X, Y, Z = x + d[0], y + d[1], z + d[2]
+        for v, n, p in ((X, nx, periodic[0]), (Y, ny, periodic[1]), (Z, nz, periodic[2])):
+            if (v < 0 or v >= n) and not p:
+                return None
+        X, Y, Z = X % nx, Y % ny, Z % nz
+        idx = X + nx * (Y + ny * Z)
+        return None if solid[idx] else idx
+
+    reads, writes = [], []
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                idx = x + nx * (y + ny * z)
+                if solid[idx]:
+                    continue
+                for i in range(q):
+                    if not odd:
+                        reads.append((i, idx))
+                        writes.append((opp[i], idx))
+                    else:
+                        s = nb(x, y, z, -c[i])
+                        reads.append((i, idx) if s is None else (opp[i], s))
+                        d = nb(x, y, z, c[i])
+                        writes.append((opp[i], idx) if d is None else (i, d))
+    return reads, writes
+
+
+@pytest.mark.parametrize("q", [15, 27])
+def test_aa_pattern_reads_and_writes_each_slot_once(q):
+    """Race freedom of the in-place streaming: per parity, the read slots and
+    the written slots are each a permutation of the fluid slots, and the odd
+    step writes exactly the slots the next even step reads (and vice versa)."""
+    from oracle import lattice as OL
+    c = (OL.D3Q15 if q == 15 else OL.D3Q27).c_np
+    # use the library's order (pairs adjacent) via sorting into pairs
+    order = [0]
+    used = {0}
+    for i in range(1, q):
+        if i in used:
+            continue
+        j = [k for k in range(q) if (c[k] == -c[i]).all()][0]
+        order += [i, j]
+        used |= {i, j}
+    c = c[order]
+    rng = np.random.default_rng(0)
+    nx, ny, nz = 5, 4, 3
+    solid = rng.uniform(size=nx * ny * nz) < 0.15
+    fluid_slots = {(i, idx) for i in range(q) for idx in range(nx * ny * nz) if not solid[idx]}
+    for periodic in ((True, False, True), (False, False, False), (True, True, True)):
+        for odd in (False, True):
+            r, w = _aa_maps(nx, ny, nz, periodic, solid, c, odd)
+            assert len(set(r)) == len(r) == len(fluid_slots) and set(r) == fluid_slots
+            assert len(set(w)) == len(w) == len(fluid_slots) and set(w) == fluid_slots

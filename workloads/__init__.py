@@ -193,7 +193,7 @@ def config4(scale: int = 1) -> Workload:
 
 def random_state(nx: int, ny: int, nz: int, *, periodic=(True, False, True), seed: int = 7,
                  params: Optional[Params] = None, solid_fraction: float = 0.0,
-                 u_amp: float = 0.02, p_amp: float = 1e-3, steps: int = 10,
+                 u_amp: float = 0.005, p_amp: float = 1e-4, steps: int = 10,
                  name: str = "random") -> Workload:
     """Smooth random phase field plus random velocity/pressure, optional random solids.
 
@@ -202,7 +202,7 @@ def random_state(nx: int, ny: int, nz: int, *, periodic=(True, False, True), see
     """
     rng = np.random.default_rng(seed)
     p = params or Params(tau_H=0.6, tau_L=0.8, mobility=0.05, xi=4.0, sigma=2e-4,
-                         g=(1e-6, -2e-6, 5e-7))
+                         rho_L=0.1, g=(1e-6, -2e-6, 5e-7))
     x, y, z = _centres(nx, ny, nz)
     field = np.zeros((nz, ny, nx))
     for _ in range(4):
