@@ -91,6 +91,8 @@ typedef struct {
   double s_high;          /* MRT rate of moments of degree >= 3 (0 < s < 2)        */
   double fp16_scale_log2[2]; /* FP16S storage exponents k for h and g (integers,
                              |k| <= 24); ignored by the other precisions          */
+  double normal_eps;      /* > 0: n = grad phi / sqrt(|grad phi|^2 + eps^2); 1e-4 is
+                             the reference choice (see the design notes)          */
 } pflbm_params;
 
 /* Bytes of device workspace for a context with this description (256-aligned
@@ -109,7 +111,8 @@ pflbm_status pflbm_create(const pflbm_desc* desc, void* d_workspace, size_t byte
 pflbm_status pflbm_destroy(pflbm_ctx* ctx);
 
 /* Validates and sets the physical parameters (tau > 1/2, M > 0, xi > 0,
- * sigma >= 0, rho > 0, 0 < s_high < 2).  Takes effect for the next step. */
+ * sigma >= 0, rho > 0, 0 < s_high < 2, normal_eps > 0).  Takes effect for the
+ * next step. */
 pflbm_status pflbm_set_params(pflbm_ctx* ctx, const pflbm_params* params);
 
 /* Copies an N-byte solid mask (1 = solid, 0 = fluid) into the workspace

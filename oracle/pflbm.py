@@ -18,6 +18,10 @@ One step n -> n+1 (paper sec. "Conservative Allen-Cahn model"):
       the same stencil since sum_k w_k c_k = 0, and is exactly zero on a
       uniform field, so rounding cannot feed the normalised n below)
   S4  n = grad phi / sqrt(|grad phi|^2 + eps^2) ; theta = 4 phi (1-phi) / xi
+      (the paper's n = grad phi / |grad phi| regularised where |grad phi| is
+      below eps, default 1e-4: far outside the interface, where theta is also
+      negligible; a much smaller eps makes the derivative of the step blow up on
+      rounding noise in the bulk over long rollouts)
   S5  rho(phi), tau(phi) by linear interpolation, omega = 1/tau
   S6  mu_phi = 4 beta phi (phi-1)(phi-1/2) - kappa lap phi,
       beta = 12 sigma/xi, kappa = 3 sigma xi / 2
@@ -57,7 +61,6 @@ import torch
 from .lattice import CS2, D3Q15, D3Q27, Lattice
 
 Num = Union[float, torch.Tensor]
-EPS_NORMAL = 1e-12
 F64 = torch.float64
 
 
@@ -73,11 +76,12 @@ class OracleParams:
     g: tuple
     s_high: float = 1.0
     collision: str = "mrt"  # "mrt" or "bgk"
+    eps_normal: float = 1e-4
 
     @classmethod
     def from_workload(cls, p, collision="mrt") -> "OracleParams":
         return cls(p.tau_H, p.tau_L, p.mobility, p.xi, p.sigma, p.rho_H, p.rho_L,
-                   tuple(p.g), p.s_high, collision)
+                   tuple(p.g), p.s_high, collision, p.normal_eps)
 
 
 class Grid:
@@ -167,7 +171,7 @@ def collide(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
         grad = grad + 3.0 * LG.w[k] * LG.c[k][:, None] * (phik - phi)[None, :]
         lap = lap + 6.0 * LG.w[k] * (phik - phi)
     # S4
-    normal = grad / torch.sqrt((grad * grad).sum(0) + EPS_NORMAL ** 2)
+    normal = grad / torch.sqrt((grad * grad).sum(0) + prm.eps_normal ** 2)
     if math.isinf(prm.xi):
         theta = torch.zeros(N, dtype=F64)
     else:

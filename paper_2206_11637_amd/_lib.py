@@ -22,7 +22,7 @@ class Params(C.Structure):
     _fields_ = [("tau_H", C.c_double), ("tau_L", C.c_double), ("mobility", C.c_double),
                 ("xi", C.c_double), ("sigma", C.c_double), ("rho_H", C.c_double),
                 ("rho_L", C.c_double), ("g", C.c_double * 3), ("s_high", C.c_double),
-                ("fp16_scale_log2", C.c_double * 2)]
+                ("fp16_scale_log2", C.c_double * 2), ("normal_eps", C.c_double)]
 
 
 # name: (restype, argtypes)
@@ -60,11 +60,13 @@ SIGNATURES = {
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Load libpflbm.so; raises if it is missing (there is no fallback path)."""
+def load(path: str = None):
+    """Load libpflbm.so (or the build named by $PFLBM_LIBRARY); raises if it is
+    missing (there is no fallback path)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("PFLBM_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build it with `python -m paper_2206_11637_amd.build` "

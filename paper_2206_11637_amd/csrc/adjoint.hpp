@@ -1,3 +1,512 @@
-// Reverse-mode kernels (filled in below the forward path).
+// Reverse mode of the coupled phase-field LBM step.
+//
+// One forward step maps the post-streaming state (h^n, g^n) to (h^{n+1},
+// g^{n+1}); the phase field phi^n = sum_i h_i^n enters each cell twice: through
+// the cell's own phi (density, relaxation time, counter-term, chemical
+// potential, equilibria) and through the grad/lap stencils of its neighbours.
+// The adjoint of a time level is therefore kept as
+//     Lambda_h,i(x) = lam_h,i(x) + a_phi(x),   Lambda_g,i(x) = lam_g,i(x)
+// where lam are the per-cell parts and a_phi the stencil part (dL/dphi^n
+// through neighbours' stencils plus any loss sensitivity to phi^n).
+//
+// Reverse step n+1 -> n (two kernels, no atomics, deterministic):
+//   k_adj_cell   pull the post-collision adjoints through the transposed
+//                streaming (Lambda of the slot each f*_i(x) was streamed to:
+//                (i, x + c_i), or (opp i, x) after a bounce-back), recompute
+//                the forward cell arithmetic from the saved primal state, and
+//                apply its vector-Jacobian product; writes lam^n, the stencil
+//                adjoints s(x) = (dL/d grad phi, dL/d lap phi) and FP64 block
+//                sums of dL/domega_phi and dL/dsigma.
+//   k_adj_stencil  a_phi^n(y) = sum over valid neighbours m of
+//                -3 w_m c_m . (s_G(y + c_m) + s_G(y)) + 6 w_m (s_L(y + c_m) - s_L(y)),
+//                the transpose of grad phi = 3 sum w c (phi_m - phi) and
+//                lap phi = 6 sum w (phi_m - phi) with the wall rule.
 #pragma once
 #include "kernels.hpp"
+
+namespace pflbm {
+
+template <typename R>
+struct AdjConst {
+  R beta4_per_sigma;   // 48 / xi  (0 if xi = inf)
+  R kappa_per_sigma;   // 3 xi / 2 (0 if xi = inf)
+};
+
+// d(H_i : A)/dA for the symmetric storage xx yy zz xy xz yz (off-diagonals
+// appear twice in the full contraction)
+template <typename R>
+__device__ __forceinline__ void hermite2_grad(Dir d, R coef, Sym<R>& acc) {
+  const R t = -coef * (R(1) / R(3));
+  acc.xx += t + (d.x ? coef : R(0));
+  acc.yy += t + (d.y ? coef : R(0));
+  acc.zz += t + (d.z ? coef : R(0));
+  if (d.x * d.y) acc.xy += (d.x * d.y > 0) ? R(2) * coef : -R(2) * coef;
+  if (d.x * d.z) acc.xz += (d.x * d.z > 0) ? R(2) * coef : -R(2) * coef;
+  if (d.y * d.z) acc.yz += (d.y * d.z > 0) ? R(2) * coef : -R(2) * coef;
+}
+
+// sum_c lamPi_c (c c)_c for one direction (the transpose of Pi = sum c c f)
+template <typename R>
+__device__ __forceinline__ R second_moment_t(Dir d, const Sym<R>& L) {
+  R r = R(0);
+  if (d.x) r += L.xx;
+  if (d.y) r += L.yy;
+  if (d.z) r += L.zz;
+  if (d.x * d.y) r += (d.x * d.y > 0) ? L.xy : -L.xy;
+  if (d.x * d.z) r += (d.x * d.z > 0) ? L.xz : -L.xz;
+  if (d.y * d.z) r += (d.y * d.z > 0) ? L.yz : -L.yz;
+  return r;
+}
+
+// Vector-Jacobian product of one cell's collision (S1-S15).  lh, lg: in =
+// adjoints of the post-collision populations, out = adjoints of the
+// pre-collision ones (the cell-local part).  Outputs the adjoints of the
+// stencil inputs (grad phi, lap phi) and of omega_phi and sigma.
+template <typename R, bool MRT>
+__device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R Gx, R Gy, R Gz,
+                                         R lap, const Phys<R>& P, const AdjConst<R>& K,
+                                         R (&lh)[Q_H], R (&lg)[Q_G], R& lGx, R& lGy, R& lGz,
+                                         R& lL, R& l_omphi, R& l_sigma) {
+  // ---------------- forward recomputation ----------------
+  const R phi = sum_h(h);
+  const R rho = P.rho_L + phi * P.drho;
+  const R om = R(1) / (P.tau_L + phi * P.dtau);
+  const R theta = P.theta_k * phi * (R(1) - phi);
+  const R rn = R(1) / sqrt(Gx * Gx + Gy * Gy + Gz * Gz + P.eps2);
+  const R nx = Gx * rn, ny = Gy * rn, nz = Gz * rn;
+  const R p3c = phi * (phi - R(1)) * (phi - R(0.5));
+  const R mu = P.beta4 * p3c - P.kappa * lap;
+  R p = R(0), jx = R(0), jy = R(0), jz = R(0);
+  Sym<R> Pi{R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    const Dir d = cg(i);
+    const R v = g[i];
+    p += v;
+    if (d.x) { jx += d.x > 0 ? v : -v; Pi.xx += v; }
+    if (d.y) { jy += d.y > 0 ? v : -v; Pi.yy += v; }
+    if (d.z) { jz += d.z > 0 ? v : -v; Pi.zz += v; }
+    if (d.x * d.y) Pi.xy += (d.x * d.y > 0) ? v : -v;
+    if (d.x * d.z) Pi.xz += (d.x * d.z > 0) ? v : -v;
+    if (d.y * d.z) Pi.yz += (d.y * d.z > 0) ? v : -v;
+  }
+  const R third = R(1) / R(3);
+  const R cgr = mu - p * third * P.drho;
+  const R F0x = cgr * Gx + rho * P.gx, F0y = cgr * Gy + rho * P.gy, F0z = cgr * Gz + rho * P.gz;
+  const R i2 = R(0.5) / rho;
+  const R u1x = jx + F0x * i2, u1y = jy + F0y * i2, u1z = jz + F0z * i2;
+  const R p3 = p * third;
+  const Sym<R> Nq{Pi.xx - p3 - u1x * u1x, Pi.yy - p3 - u1y * u1y, Pi.zz - p3 - u1z * u1z,
+                  Pi.xy - u1x * u1y, Pi.xz - u1x * u1z, Pi.yz - u1y * u1z};
+  const R fm = -(R(1) - R(0.5) * om) * P.drho;
+  const R NGx = Nq.xx * Gx + Nq.xy * Gy + Nq.xz * Gz;
+  const R NGy = Nq.xy * Gx + Nq.yy * Gy + Nq.yz * Gz;
+  const R NGz = Nq.xz * Gx + Nq.yz * Gy + Nq.zz * Gz;
+  const R Fx = F0x + fm * NGx, Fy = F0y + fm * NGy, Fz = F0z + fm * NGz;
+  const R ux = jx + Fx * i2, uy = jy + Fy * i2, uz = jz + Fz * i2;
+  const R uu = ux * ux + uy * uy + uz * uz;
+
+  // ---------------- phase-field collision, reverse ----------------
+  const R omp = P.omega_phi;
+  const R fkh = (R(1) - R(0.5) * omp) * theta;
+  const R sh = MRT ? P.s_high : omp;
+  const R dloh = omp - sh;
+  R a1hx = R(0), a1hy = R(0), a1hz = R(0);
+  Sym<R> A2h{R(0), R(0), R(0), R(0), R(0), R(0)};
+  if (MRT) {
+    R hx = R(0), hy = R(0), hz = R(0);
+    Sym<R> Ph{R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 0; i < Q_H; ++i) {
+      const Dir d = ch(i);
+      const R v = h[i];
+      if (d.x) { hx += d.x > 0 ? v : -v; Ph.xx += v; }
+      if (d.y) { hy += d.y > 0 ? v : -v; Ph.yy += v; }
+      if (d.z) { hz += d.z > 0 ? v : -v; Ph.zz += v; }
+      if (d.x * d.y) Ph.xy += (d.x * d.y > 0) ? v : -v;
+      if (d.x * d.z) Ph.xz += (d.x * d.z > 0) ? v : -v;
+      if (d.y * d.z) Ph.yz += (d.y * d.z > 0) ? v : -v;
+    }
+    a1hx = phi * ux - hx;
+    a1hy = phi * uy - hy;
+    a1hz = phi * uz - hz;
+    const R pp3 = phi * third;
+    A2h = Sym<R>{pp3 + phi * ux * ux - Ph.xx, pp3 + phi * uy * uy - Ph.yy, pp3 + phi * uz * uz - Ph.zz,
+                 phi * ux * uy - Ph.xy, phi * ux * uz - Ph.xz, phi * uy * uz - Ph.yz};
+  }
+  const R hbase = R(1) - R(1.5) * uu;
+  R l_phi = R(0), l_hbase = R(0), l_fkh = R(0);
+  R lux = R(0), luy = R(0), luz = R(0);
+  R lnx = R(0), lny = R(0), lnz = R(0);
+  R la1hx = R(0), la1hy = R(0), la1hz = R(0);
+  Sym<R> lA2h{R(0), R(0), R(0), R(0), R(0), R(0)};
+  R lomp = R(0);
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    const Dir d = ch(i);
+    const R w = R(wh(i));
+    const R lam = lh[i];
+    const R cu = dot(d, ux, uy, uz);
+    const R e = hbase + cu * (R(3) + R(4.5) * cu);
+    const R cn = dot(d, nx, ny, nz);
+    const R lheq = sh * lam;
+    l_phi += lheq * w * e;
+    l_hbase += lheq * w * phi;
+    const R lcu = lheq * w * phi * (R(3) + R(9) * cu);
+    if (d.x) lux += d.x > 0 ? lcu : -lcu;
+    if (d.y) luy += d.y > 0 ? lcu : -lcu;
+    if (d.z) luz += d.z > 0 ? lcu : -lcu;
+    l_fkh += lam * w * cn;
+    const R ln = lam * w * fkh;
+    if (d.x) lnx += d.x > 0 ? ln : -ln;
+    if (d.y) lny += d.y > 0 ? ln : -ln;
+    if (d.z) lnz += d.z > 0 ? ln : -ln;
+    if (MRT) {
+      const R proj = w * (R(3) * dot(d, a1hx, a1hy, a1hz) + R(4.5) * hermite2(d, A2h));
+      const R lproj = dloh * lam * w;
+      const R l3 = R(3) * lproj;
+      if (d.x) la1hx += d.x > 0 ? l3 : -l3;
+      if (d.y) la1hy += d.y > 0 ? l3 : -l3;
+      if (d.z) la1hz += d.z > 0 ? l3 : -l3;
+      hermite2_grad(d, R(4.5) * lproj, lA2h);
+      lomp += lam * proj;
+    } else {
+      lomp += lam * (w * phi * e - h[i]);
+    }
+    lomp -= lam * R(0.5) * theta * w * cn;
+  }
+  const R l_theta = (R(1) - R(0.5) * omp) * l_fkh;
+  R lhjx = R(0), lhjy = R(0), lhjz = R(0);
+  Sym<R> lPh{R(0), R(0), R(0), R(0), R(0), R(0)};
+  if (MRT) {
+    l_phi += la1hx * ux + la1hy * uy + la1hz * uz + (lA2h.xx + lA2h.yy + lA2h.zz) * third +
+             lA2h.xx * ux * ux + lA2h.yy * uy * uy + lA2h.zz * uz * uz + lA2h.xy * ux * uy +
+             lA2h.xz * ux * uz + lA2h.yz * uy * uz;
+    lux += phi * (la1hx + R(2) * lA2h.xx * ux + lA2h.xy * uy + lA2h.xz * uz);
+    luy += phi * (la1hy + R(2) * lA2h.yy * uy + lA2h.xy * ux + lA2h.yz * uz);
+    luz += phi * (la1hz + R(2) * lA2h.zz * uz + lA2h.xz * ux + lA2h.yz * uy);
+    lhjx = -la1hx;
+    lhjy = -la1hy;
+    lhjz = -la1hz;
+    lPh = Sym<R>{-lA2h.xx, -lA2h.yy, -lA2h.zz, -lA2h.xy, -lA2h.xz, -lA2h.yz};
+  }
+  R l_uu = -R(1.5) * l_hbase;
+
+  // ---------------- hydrodynamic collision, reverse ----------------
+  const R fk = (R(1) - R(0.5) * om) * R(3) / rho;
+  const R base = p - R(1.5) * uu;
+  const R s = MRT ? P.s_high : om;
+  const R dlo = om - s;
+  const R a1x = ux - jx, a1y = uy - jy, a1z = uz - jz;
+  const Sym<R> A2{p3 + ux * ux - Pi.xx, p3 + uy * uy - Pi.yy, p3 + uz * uz - Pi.zz,
+                  ux * uy - Pi.xy, ux * uz - Pi.xz, uy * uz - Pi.yz};
+  R l_base = R(0), l_fk = R(0), lFx = R(0), lFy = R(0), lFz = R(0), lom = R(0);
+  R la1x = R(0), la1y = R(0), la1z = R(0);
+  Sym<R> lA2{R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    const Dir d = cg(i);
+    const R w = R(wg(i));
+    const R lam = lg[i];
+    const R cu = dot(d, ux, uy, uz);
+    const R lgeq = s * lam * w;
+    l_base += lgeq;
+    const R lcu = lgeq * (R(3) + R(9) * cu);
+    if (d.x) lux += d.x > 0 ? lcu : -lcu;
+    if (d.y) luy += d.y > 0 ? lcu : -lcu;
+    if (d.z) luz += d.z > 0 ? lcu : -lcu;
+    l_fk += lam * w * dot(d, Fx, Fy, Fz);
+    const R lf = lam * w * fk;
+    if (d.x) lFx += d.x > 0 ? lf : -lf;
+    if (d.y) lFy += d.y > 0 ? lf : -lf;
+    if (d.z) lFz += d.z > 0 ? lf : -lf;
+    if (MRT) {
+      const R proj = w * (R(3) * dot(d, a1x, a1y, a1z) + R(4.5) * hermite2(d, A2));
+      const R lproj = dlo * lam * w;
+      const R l3 = R(3) * lproj;
+      if (d.x) la1x += d.x > 0 ? l3 : -l3;
+      if (d.y) la1y += d.y > 0 ? l3 : -l3;
+      if (d.z) la1z += d.z > 0 ? l3 : -l3;
+      hermite2_grad(d, R(4.5) * lproj, lA2);
+      lom += lam * proj;
+    } else {
+      lom += lam * (w * (base + cu * (R(3) + R(4.5) * cu)) - g[i]);
+    }
+  }
+  lom += l_fk * (-R(1.5) / rho);
+  R l_rho = -l_fk * fk / rho;
+  R l_p = l_base;
+  l_uu += -R(1.5) * l_base;
+  R ljx = R(0), ljy = R(0), ljz = R(0);
+  Sym<R> lPi{R(0), R(0), R(0), R(0), R(0), R(0)};
+  if (MRT) {
+    lux += la1x + R(2) * lA2.xx * ux + lA2.xy * uy + lA2.xz * uz;
+    luy += la1y + R(2) * lA2.yy * uy + lA2.xy * ux + lA2.yz * uz;
+    luz += la1z + R(2) * lA2.zz * uz + lA2.xz * ux + lA2.yz * uy;
+    ljx -= la1x;
+    ljy -= la1y;
+    ljz -= la1z;
+    l_p += (lA2.xx + lA2.yy + lA2.zz) * third;
+    lPi = Sym<R>{-lA2.xx, -lA2.yy, -lA2.zz, -lA2.xy, -lA2.xz, -lA2.yz};
+  }
+  lux += R(2) * ux * l_uu;
+  luy += R(2) * uy * l_uu;
+  luz += R(2) * uz * l_uu;
+
+  // ---------------- force prologue, reverse ----------------
+  // u = j + F i2
+  ljx += lux; ljy += luy; ljz += luz;
+  lFx += lux * i2; lFy += luy * i2; lFz += luz * i2;
+  R l_i2 = lux * Fx + luy * Fy + luz * Fz;
+  // F = F0 + fm N G
+  R lF0x = lFx, lF0y = lFy, lF0z = lFz;
+  const R l_fm = lFx * NGx + lFy * NGy + lFz * NGz;
+  const Sym<R> lN{fm * lFx * Gx, fm * lFy * Gy, fm * lFz * Gz, fm * (lFx * Gy + lFy * Gx),
+                  fm * (lFx * Gz + lFz * Gx), fm * (lFy * Gz + lFz * Gy)};
+  lGx = fm * (Nq.xx * lFx + Nq.xy * lFy + Nq.xz * lFz);
+  lGy = fm * (Nq.xy * lFx + Nq.yy * lFy + Nq.yz * lFz);
+  lGz = fm * (Nq.xz * lFx + Nq.yz * lFy + Nq.zz * lFz);
+  lom += R(0.5) * P.drho * l_fm;
+  // N = Pi - p/3 I - u1 u1^T
+  lPi.xx += lN.xx; lPi.yy += lN.yy; lPi.zz += lN.zz;
+  lPi.xy += lN.xy; lPi.xz += lN.xz; lPi.yz += lN.yz;
+  l_p -= (lN.xx + lN.yy + lN.zz) * third;
+  const R lu1x = -(R(2) * lN.xx * u1x + lN.xy * u1y + lN.xz * u1z);
+  const R lu1y = -(R(2) * lN.yy * u1y + lN.xy * u1x + lN.yz * u1z);
+  const R lu1z = -(R(2) * lN.zz * u1z + lN.xz * u1x + lN.yz * u1y);
+  // u1 = j + F0 i2
+  ljx += lu1x; ljy += lu1y; ljz += lu1z;
+  lF0x += lu1x * i2; lF0y += lu1y * i2; lF0z += lu1z * i2;
+  l_i2 += lu1x * F0x + lu1y * F0y + lu1z * F0z;
+  // i2 = 1/(2 rho)
+  l_rho += -l_i2 * i2 / rho;
+  // F0 = cgr G + rho g
+  const R l_cgr = lF0x * Gx + lF0y * Gy + lF0z * Gz;
+  lGx += cgr * lF0x; lGy += cgr * lF0y; lGz += cgr * lF0z;
+  l_rho += lF0x * P.gx + lF0y * P.gy + lF0z * P.gz;
+  // cgr = mu - p drho / 3
+  const R l_mu = l_cgr;
+  l_p -= P.drho * third * l_cgr;
+  // mu = beta4 p3c(phi) - kappa lap
+  l_phi += l_mu * P.beta4 * (R(3) * phi * phi - R(3) * phi + R(0.5));
+  lL = -P.kappa * l_mu;
+  l_sigma = l_mu * (K.beta4_per_sigma * p3c - K.kappa_per_sigma * lap);
+  // n = G rn
+  const R Gln = Gx * lnx + Gy * lny + Gz * lnz;
+  const R rn3 = rn * rn * rn;
+  lGx += rn * lnx - rn3 * Gln * Gx;
+  lGy += rn * lny - rn3 * Gln * Gy;
+  lGz += rn * lnz - rn3 * Gln * Gz;
+  // theta, omega, rho of phi
+  l_phi += l_theta * P.theta_k * (R(1) - R(2) * phi);
+  l_phi += -lom * om * om * P.dtau;
+  l_phi += l_rho * P.drho;
+  l_omphi = lomp;
+
+  // ---------------- adjoints of the pre-collision populations ----------------
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    const Dir d = cg(i);
+    lg[i] = (R(1) - s) * lg[i] + l_p + dot(d, ljx, ljy, ljz) + second_moment_t(d, lPi);
+  }
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    const Dir d = ch(i);
+    R v = (R(1) - sh) * lh[i] + l_phi;
+    if (MRT) v += dot(d, lhjx, lhjy, lhjz) + second_moment_t(d, lPh);
+    lh[i] = v;
+  }
+}
+
+template <typename S>
+struct AdjArgs {
+  using R = typename Store<S>::R;
+  // primal state of level n (a saved state: populations in the AA layout of
+  // step n's parity, then the phi field)
+  const S* ph;
+  const S* pg;
+  const R* pphi;
+  const unsigned char* mask;
+  // adjoint of level n+1 (natural layout) and of level n
+  const R* lh_in;
+  const R* lg_in;
+  const R* aphi_in;
+  R* lh_out;
+  R* lg_out;
+  R* sadj;          // [4][N]: dL/d(grad phi x, y, z), dL/d(lap phi)
+  double* gsum;     // [nblocks][2] running sums of dL/domega_phi, dL/dsigma
+  Geom geo;
+  Phys<R> P;
+  AdjConst<R> K;
+  Codec<R> cd;
+};
+
+template <typename S, bool MRT, bool ODD, bool MASK>
+__global__ __launch_bounds__(256) void k_adj_cell(AdjArgs<S> a) {
+  using R = typename Store<S>::R;
+  extern __shared__ unsigned char smem_raw[];
+  R* tile = reinterpret_cast<R*>(smem_raw);
+  __shared__ double red[4][2];
+  const Geom& G = a.geo;
+  const TileCoord t = tile_of_block(G);
+  load_phi_tile<R, MASK>(tile, a.pphi, a.mask, G, t);
+  __syncthreads();
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
+  const int TX = G.bx + 2, TY = G.by + 2;
+  double acc0 = 0.0, acc1 = 0.0;
+  if (x < G.nx && y < G.ny && tile[(TY + ly + 1) * TX + lx + 1] != sentinel<R>()) {
+    const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
+    const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
+    const Nbhd nb = make_nbhd(x, y, z, G);
+    R h[Q_H], g[Q_G];
+    load_pops<S, ODD>(a.ph, a.pg, G.N, idx, nb, walls, a.cd, h, g);
+    R Gx, Gy, Gz, lap;
+    stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
+    // transposed streaming: Lambda of the slot each post-collision value went to
+    R lh[Q_H], lg[Q_G];
+#pragma unroll
+    for (int i = 0; i < Q_H; ++i) {
+      const Dir d = ch(i);
+      unsigned cell = idx;
+      int pop = opp(i);
+      if (!(walls & (1u << nb27(d.x, d.y, d.z)))) {
+        cell = nb.at(d.x, d.y, d.z);
+        pop = i;
+      }
+      lh[i] = *slot(a.lh_in, G.N, pop, cell) + a.aphi_in[cell];
+    }
+#pragma unroll
+    for (int i = 0; i < Q_G; ++i) {
+      const Dir d = cg(i);
+      unsigned cell = idx;
+      int pop = opp(i);
+      if (!(walls & (1u << nb27(d.x, d.y, d.z)))) {
+        cell = nb.at(d.x, d.y, d.z);
+        pop = i;
+      }
+      lg[i] = *slot(a.lg_in, G.N, pop, cell);
+    }
+    R lGx, lGy, lGz, lL, lomp, lsig;
+    cell_vjp<R, MRT>(h, g, Gx, Gy, Gz, lap, a.P, a.K, lh, lg, lGx, lGy, lGz, lL, lomp, lsig);
+#pragma unroll
+    for (int i = 0; i < Q_H; ++i) *slot(a.lh_out, G.N, i, idx) = lh[i];
+#pragma unroll
+    for (int i = 0; i < Q_G; ++i) *slot(a.lg_out, G.N, i, idx) = lg[i];
+    *slot(a.sadj, G.N, 0, idx) = lGx;
+    *slot(a.sadj, G.N, 1, idx) = lGy;
+    *slot(a.sadj, G.N, 2, idx) = lGz;
+    *slot(a.sadj, G.N, 3, idx) = lL;
+    acc0 = double(lomp);
+    acc1 = double(lsig);
+  }
+  // FP64 block sums in a fixed order, added to this block's running slot
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    acc0 += __shfl_xor(acc0, off, 64);
+    acc1 += __shfl_xor(acc1, off, 64);
+  }
+  const int tid = threadIdx.x + threadIdx.y * G.bx;
+  if ((tid & 63) == 0) {
+    red[tid >> 6][0] = acc0;
+    red[tid >> 6][1] = acc1;
+  }
+  __syncthreads();
+  if (tid < 2) {
+    const double v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    a.gsum[(long long)blockIdx.x * 2 + tid] += v;
+  }
+}
+
+template <typename R>
+struct AdjStencilArgs {
+  const R* sadj;      // [4][N]
+  const unsigned char* mask;
+  R* aphi_out;        // [N]
+  Geom geo;
+};
+
+// a_phi(y) = sum_m valid(y, m) [-3 w_m c_m.(s_G(y+c_m) + s_G(y)) + 6 w_m (s_L(y+c_m) - s_L(y))]
+template <typename R, bool MASK>
+__global__ __launch_bounds__(256) void k_adj_stencil(AdjStencilArgs<R> a) {
+  extern __shared__ unsigned char smem_raw[];
+  const Geom& G = a.geo;
+  const int TX = G.bx + 2, TY = G.by + 2, total = TX * TY * 3;
+  R* ts = reinterpret_cast<R*>(smem_raw);                       // [4][total]
+  unsigned char* tv = reinterpret_cast<unsigned char*>(ts + 4 * total);   // validity
+  const TileCoord t = tile_of_block(G);
+  const int tid = threadIdx.x + threadIdx.y * G.bx;
+  for (int e = tid; e < total; e += 256) {
+    const int ix = e % TX, r = e / TX, iy = r % TY, iz = r / TY;
+    int X = t.x0 - 1 + ix, Y = t.y0 - 1 + iy, Z = t.z - 1 + iz;
+    unsigned char ok = 0;
+    R v0 = R(0), v1 = R(0), v2 = R(0), v3 = R(0);
+    if (wrap(X, G.nx, G.px) && wrap(Y, G.ny, G.py) && wrap(Z, G.nz, G.pz)) {
+      const unsigned id = X + (unsigned)G.nx * (Y + (unsigned)G.ny * Z);
+      if (!MASK || !a.mask[id]) {
+        ok = 1;
+        v0 = *slot(a.sadj, G.N, 0, id);
+        v1 = *slot(a.sadj, G.N, 1, id);
+        v2 = *slot(a.sadj, G.N, 2, id);
+        v3 = *slot(a.sadj, G.N, 3, id);
+      }
+    }
+    ts[e] = v0;
+    ts[total + e] = v1;
+    ts[2 * total + e] = v2;
+    ts[3 * total + e] = v3;
+    tv[e] = ok;
+  }
+  __syncthreads();
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const int c0 = (TY + ly + 1) * TX + lx + 1;
+  if (!tv[c0]) return;
+  const R sx = ts[c0], sy = ts[total + c0], sz = ts[2 * total + c0], sl = ts[3 * total + c0];
+  R acc = R(0);
+#pragma unroll
+  for (int k = 1; k < 27; ++k) {
+    const Dir d = cg(k);
+    const int e = ((1 + d.z) * TY + (ly + 1 + d.y)) * TX + (lx + 1 + d.x);
+    if (tv[e]) {
+      const R w = R(wg(k));
+      const R gsum = dot(d, ts[e] + sx, ts[total + e] + sy, ts[2 * total + e] + sz);
+      acc += R(-3) * w * gsum + R(6) * w * (ts[3 * total + e] - sl);
+    }
+  }
+  const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
+  a.aphi_out[idx] = acc;
+}
+
+// a_phi += dL/dphi (FP64 input)
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_inject(R* __restrict__ aphi, const double* __restrict__ d,
+                                                     long long N) {
+  const long long i = blockIdx.x * 256ll + threadIdx.x;
+  if (i < N) aphi[i] = R(double(aphi[i]) + d[i]);
+}
+
+// dL/dphi0 = sum_i (lam_h,i + a_phi) Gamma_i(u0)
+template <typename R, bool MASK>
+__global__ __launch_bounds__(256) void k_adj_init(const R* __restrict__ lh, const R* __restrict__ aphi,
+                                                   const double* __restrict__ u0,
+                                                   const unsigned char* __restrict__ mask, long long N,
+                                                   double* __restrict__ out) {
+  const long long i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= N) return;
+  if (MASK && mask[i]) { out[i] = 0.0; return; }
+  double ux = 0, uy = 0, uz = 0;
+  if (u0) { ux = u0[i]; uy = u0[N + i]; uz = u0[2 * N + i]; }
+  const R rx = R(ux), ry = R(uy), rz = R(uz);
+  const R base = R(1) - R(1.5) * (rx * rx + ry * ry + rz * rz);
+  R acc = R(0);
+#pragma unroll
+  for (int k = 0; k < Q_H; ++k) {
+    const R cu = dot(ch(k), rx, ry, rz);
+    acc += (lh[k * N + i] + aphi[i]) * R(wh(k)) * (base + cu * (R(3) + R(4.5) * cu));
+  }
+  out[i] = double(acc);
+}
+
+}  // namespace pflbm

@@ -32,7 +32,7 @@ struct Phys {
   R gx, gy, gz;       // body acceleration
   R omega_phi;        // 1 / (3 M + 1/2)
   R s_high;           // rate of degree >= 3 moments (MRT)
-  R eps2;             // regularisation of |grad phi| in n
+  R eps2;             // eps^2: n = grad phi / sqrt(|grad phi|^2 + eps^2)
 };
 
 // second-moment tensor of a population set, symmetric storage xx yy zz xy xz yz

@@ -122,10 +122,10 @@ __device__ __forceinline__ void load_phi_tile(R* tile, const R* __restrict__ phi
 
 // Linear indices of the 3x3x3 neighbourhood (periodic wrap; out-of-box
 // entries are never dereferenced because the tile marks them as walls).
+// 32-bit: the library limits N * sizeof(storage) below 2^32.
 struct Nbhd {
-  int xs[3];
-  long long ys[3], zs[3];
-  __device__ __forceinline__ long long at(int dx, int dy, int dz) const {
+  unsigned xs[3], ys[3], zs[3];
+  __device__ __forceinline__ unsigned at(int dx, int dy, int dz) const {
     return xs[dx + 1] + ys[dy + 1] + zs[dz + 1];
   }
 };
@@ -135,7 +135,7 @@ __device__ __forceinline__ Nbhd make_nbhd(int x, int y, int z, const Geom& G) {
   n.xs[0] = x == 0 ? G.nx - 1 : x - 1;
   n.xs[1] = x;
   n.xs[2] = x == G.nx - 1 ? 0 : x + 1;
-  const long long sy = G.nx, sz = (long long)G.nx * G.ny;
+  const unsigned sy = G.nx, sz = (unsigned)G.nx * (unsigned)G.ny;
   n.ys[0] = (y == 0 ? G.ny - 1 : y - 1) * sy;
   n.ys[1] = y * sy;
   n.ys[2] = (y == G.ny - 1 ? 0 : y + 1) * sy;
@@ -143,6 +143,20 @@ __device__ __forceinline__ Nbhd make_nbhd(int x, int y, int z, const Geom& G) {
   n.zs[1] = z * sz;
   n.zs[2] = (z == G.nz - 1 ? 0 : z + 1) * sz;
   return n;
+}
+
+// Address of population `pop` of cell `cell`: a wave-uniform base (scalar
+// registers) plus a 32-bit per-lane byte offset, which maps onto the
+// saddr + voffset form of global loads and stores.
+template <typename S>
+__device__ __forceinline__ S* slot(S* base, long long N, int pop, unsigned cell) {
+  char* b = reinterpret_cast<char*>(base + (long long)pop * N);
+  return reinterpret_cast<S*>(b + (unsigned)(cell * (unsigned)sizeof(S)));
+}
+template <typename S>
+__device__ __forceinline__ const S* slot(const S* base, long long N, int pop, unsigned cell) {
+  const char* b = reinterpret_cast<const char*>(base + (long long)pop * N);
+  return reinterpret_cast<const S*>(b + (unsigned)(cell * (unsigned)sizeof(S)));
 }
 
 // Bit k of the result: neighbour in direction kC27[k] is a wall or solid.
@@ -184,59 +198,71 @@ __device__ __forceinline__ void stencil(const R* tile, int TX, int TY, int lx, i
 // ---- population access (AA pattern) --------------------------------------
 template <typename S, bool ODD>
 __device__ __forceinline__ void load_pops(const S* __restrict__ H, const S* __restrict__ Gp,
-                                          long long N, long long idx, const Nbhd& nb,
+                                          long long N, unsigned idx, const Nbhd& nb,
                                           unsigned walls, const Codec<typename Store<S>::R>& cd,
                                           typename Store<S>::R (&h)[Q_H],
                                           typename Store<S>::R (&g)[Q_G]) {
   using St = Store<S>;
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
-    const int k = kH2G[i];
-    long long a = (long long)i * N + idx;
+    int pop = i;
+    unsigned cell = idx;
     if (ODD) {
       const Dir d = ch(i);
-      if (!(walls & (1u << nb27(-d.x, -d.y, -d.z))))
-        a = (long long)opp(i) * N + nb.at(-d.x, -d.y, -d.z);
+      if (!(walls & (1u << nb27(-d.x, -d.y, -d.z)))) {
+        pop = opp(i);
+        cell = nb.at(-d.x, -d.y, -d.z);
+      }
     }
-    (void)k;
-    h[i] = St::ld(H + a, cd.sh_h[i], cd.inv_scale_h);
+    h[i] = St::ld(slot(H, N, pop, cell), cd.sh_h[i], cd.inv_scale_h);
   }
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) {
-    long long a = (long long)i * N + idx;
+    int pop = i;
+    unsigned cell = idx;
     if (ODD) {
       const Dir d = cg(i);
-      if (!(walls & (1u << nb27(-d.x, -d.y, -d.z))))
-        a = (long long)opp(i) * N + nb.at(-d.x, -d.y, -d.z);
+      if (!(walls & (1u << nb27(-d.x, -d.y, -d.z)))) {
+        pop = opp(i);
+        cell = nb.at(-d.x, -d.y, -d.z);
+      }
     }
-    g[i] = St::ld(Gp + a, typename Store<S>::R(0), cd.inv_scale_g);
+    g[i] = St::ld(slot(Gp, N, pop, cell), typename Store<S>::R(0), cd.inv_scale_g);
   }
 }
 
 template <typename S, bool ODD>
 __device__ __forceinline__ void store_pops(S* __restrict__ H, S* __restrict__ Gp, long long N,
-                                           long long idx, const Nbhd& nb, unsigned walls,
+                                           unsigned idx, const Nbhd& nb, unsigned walls,
                                            const Codec<typename Store<S>::R>& cd,
                                            const typename Store<S>::R (&h)[Q_H],
                                            const typename Store<S>::R (&g)[Q_G]) {
   using St = Store<S>;
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
-    long long a = (long long)opp(i) * N + idx;
+    int pop = opp(i);
+    unsigned cell = idx;
     if (ODD) {
       const Dir d = ch(i);
-      if (!(walls & (1u << nb27(d.x, d.y, d.z)))) a = (long long)i * N + nb.at(d.x, d.y, d.z);
+      if (!(walls & (1u << nb27(d.x, d.y, d.z)))) {
+        pop = i;
+        cell = nb.at(d.x, d.y, d.z);
+      }
     }
-    St::st(H + a, h[i], cd.sh_h[i], cd.scale_h);
+    St::st(slot(H, N, pop, cell), h[i], cd.sh_h[i], cd.scale_h);
   }
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) {
-    long long a = (long long)opp(i) * N + idx;
+    int pop = opp(i);
+    unsigned cell = idx;
     if (ODD) {
       const Dir d = cg(i);
-      if (!(walls & (1u << nb27(d.x, d.y, d.z)))) a = (long long)i * N + nb.at(d.x, d.y, d.z);
+      if (!(walls & (1u << nb27(d.x, d.y, d.z)))) {
+        pop = i;
+        cell = nb.at(d.x, d.y, d.z);
+      }
     }
-    St::st(Gp + a, g[i], typename Store<S>::R(0), cd.scale_g);
+    St::st(slot(Gp, N, pop, cell), g[i], typename Store<S>::R(0), cd.scale_g);
   }
 }
 
@@ -258,10 +284,17 @@ struct CellArgs {
 
 enum Mode { MODE_STEP = 0, MODE_MOMENTS = 1 };
 
+// Occupancy request of the fused kernel: 3 waves per SIMD (<= 168 VGPRs)
+// for the FP32-arithmetic forms, measured faster than the unconstrained 2;
+// the FP64 form keeps the compiler's choice (forcing it spills).
+template <typename S>
+struct StepWaves { static constexpr int value = sizeof(S) == 8 ? 1 : 3; };
+
 // Fused collide + stream of both lattices (MODE_STEP), or the cell moments
 // with the same force prologue (MODE_MOMENTS).
 template <typename S, bool MRT, bool ODD, bool MASK, int MODE>
-__global__ __launch_bounds__(256) void k_cell(CellArgs<S> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<S>::value)))
+void k_cell(CellArgs<S> a) {
   using R = typename Store<S>::R;
   extern __shared__ unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
@@ -285,7 +318,7 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs<S> a) {
   const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
   const Nbhd nb = make_nbhd(x, y, z, G);
   R h[Q_H], g[Q_G];
-  load_pops<S, ODD>(a.h, a.g, G.N, idx, nb, walls, a.cd, h, g);
+  load_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd, h, g);
   R Gx, Gy, Gz, lap;
   stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
   CellState<R> c;
@@ -302,7 +335,7 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs<S> a) {
   }
   collide_g<R, MRT>(g, c, a.P);
   collide_h<R, MRT>(h, c, a.P);
-  store_pops<S, ODD>(a.h, a.g, G.N, idx, nb, walls, a.cd, h, g);
+  store_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd, h, g);
 }
 
 // Neighbour-is-wall bits for the populations of one cell, without LDS
@@ -366,19 +399,22 @@ __global__ __launch_bounds__(256) void k_light(LightArgs<S> a) {
         using St = Store<S>;
 #pragma unroll
         for (int i = 0; i < Q_H; ++i) {
-          long long ad = (long long)i * G.N + idx;
+          int pop = i;
+          unsigned cell = (unsigned)idx;
           if (ODD) {
             const Dir d = ch(i);
-            if (!(walls & (1u << nb27(-d.x, -d.y, -d.z))))
-              ad = (long long)opp(i) * G.N + nb.at(-d.x, -d.y, -d.z);
+            if (!(walls & (1u << nb27(-d.x, -d.y, -d.z)))) {
+              pop = opp(i);
+              cell = nb.at(-d.x, -d.y, -d.z);
+            }
           }
-          h[i] = St::ld(a.h + ad, a.cd.sh_h[i], a.cd.inv_scale_h);
+          h[i] = St::ld(slot(a.h, G.N, pop, cell), a.cd.sh_h[i], a.cd.inv_scale_h);
         }
         const R s = sum_h(h);
         a.phi_out[idx] = s;
         if (a.out_phi64) a.out_phi64[idx] = double(s);
       } else {
-        load_pops<S, ODD>(a.h, a.g, G.N, idx, nb, walls, a.cd, h, g);
+        load_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd, h, g);
         if (LM == LM_READ_POPS) {
 #pragma unroll
           for (int i = 0; i < Q_H; ++i) a.out_h[i * G.N + idx] = double(h[i]);

@@ -33,7 +33,9 @@ bool desc_ok(const pflbm_desc* d) {
   if (d->collision < 0 || d->collision > 1) return false;
   if (d->periodic > 7u) return false;
   const long long N = (long long)d->nx * d->ny * d->nz;
-  if (N > (1ll << 31) - 1) return false;
+  // population addressing uses 32-bit byte offsets within each population
+  const long long per_pop = N * (long long)(d->precision == PFLBM_FP64 ? 8 : 4);
+  if (per_pop >= (1ll << 32)) return false;
   return true;
 }
 
@@ -156,7 +158,7 @@ Phys<R> make_phys(const pflbm_params& p) {
   P.gx = R(p.g[0]); P.gy = R(p.g[1]); P.gz = R(p.g[2]);
   P.omega_phi = R(1.0 / (3.0 * p.mobility + 0.5));
   P.s_high = R(p.s_high);
-  P.eps2 = R(1e-24);
+  P.eps2 = R(p.normal_eps * p.normal_eps);
   return P;
 }
 
@@ -380,6 +382,8 @@ pflbm_status params_ok(const pflbm_params* p, std::string& why) {
   if (bad(!(p->sigma >= 0) || !std::isfinite(p->sigma), "sigma must be >= 0")) return PFLBM_ERR_ARG;
   if (bad(!(p->rho_H > 0) || !(p->rho_L > 0), "densities must be > 0")) return PFLBM_ERR_ARG;
   if (bad(!(p->s_high > 0 && p->s_high < 2), "s_high must lie in (0, 2)")) return PFLBM_ERR_ARG;
+  if (bad(!(p->normal_eps > 0) || !std::isfinite(p->normal_eps), "normal_eps must be > 0"))
+    return PFLBM_ERR_ARG;
   for (int k = 0; k < 3; ++k)
     if (bad(!std::isfinite(p->g[k]), "g must be finite")) return PFLBM_ERR_ARG;
   for (int k = 0; k < 2; ++k) {
@@ -423,6 +427,7 @@ pflbm_status pflbm_create(const pflbm_desc* desc, void* d_workspace, size_t byte
   p.s_high = 1.0;
   p.fp16_scale_log2[0] = 8;
   p.fp16_scale_log2[1] = 12;
+  p.normal_eps = 1e-4;
   c->p = p;
   *out = c;
   return PFLBM_OK;

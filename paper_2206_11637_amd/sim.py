@@ -36,6 +36,7 @@ def _params_struct(p) -> Params:
     s.s_high = get("s_high")
     for k, v in enumerate(get("fp16_scale_log2")):
         s.fp16_scale_log2[k] = v
+    s.normal_eps = get("normal_eps")
     return s
 
 

@@ -1,0 +1,176 @@
+"""Reverse mode on the GPU: parity with the oracle's autograd (FP64), central
+finite differences, and the reduced-precision gradient errors."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint as AD
+from oracle import pflbm as OP
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grads(wl, precision, collision, nsteps, K, depth, target, ckpt=None, M=None, sigma=None,
+               stats=None):
+    from paper_2206_11637_amd.rollout import amplitude_rollout
+    from paper_2206_11637_amd.sim import Simulation
+    sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, precision, collision, wl.solid, wl.params)
+    dev = sim.device
+    phi0 = torch.tensor(wl.phi0, dtype=torch.float64, device=dev, requires_grad=True)
+    Mt = torch.tensor(M if M is not None else wl.params.mobility, dtype=torch.float64, device=dev,
+                      requires_grad=True)
+    st = torch.tensor(sigma if sigma is not None else wl.params.sigma, dtype=torch.float64,
+                      device=dev, requires_grad=True)
+    trace = amplitude_rollout(sim, phi0, Mt, st, params=wl.params, nsteps=nsteps, sample_every=K,
+                              depth=depth, u0=wl.u0, pstar0=wl.pstar0, checkpoint_every=ckpt,
+                              stats=stats)
+    L = ((trace - torch.as_tensor(target, device=dev)) ** 2).sum()
+    L.backward()
+    return L.item(), phi0.grad.reshape(-1).cpu(), Mt.grad.item(), st.grad.item(), trace.detach().cpu()
+
+
+def _small(collision, solids):
+    wl = W.capillary_wave(16, 24, 6, depth=12.0, amplitude=1.5, xi=4.0, noise=1e-6,
+                          params=W.Params(tau_H=0.6, tau_L=0.7, mobility=0.05, sigma=2e-3,
+                                          rho_L=0.05, g=(0.0, -1e-5, 0.0)))
+    if solids:
+        rng = np.random.default_rng(12)
+        solid = rng.uniform(size=(wl.nz, wl.ny, wl.nx)) < 0.05
+        solid[:, :, 0] = False            # keep the probe column fluid
+        wl = dataclasses.replace(wl, solid=solid, phi0=np.where(solid, 0.0, wl.phi0))
+    return wl
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("solids,nsteps,ckpt", [(False, 24, 5), (True, 23, 4), (False, 9, None)])
+def test_fp64_adjoint_matches_oracle_autograd(collision, solids, nsteps, ckpt):
+    wl = _small(collision, solids)
+    K = 3 if nsteps % 3 == 0 else 1
+    rng = np.random.default_rng(5)
+    target = rng.normal(0, 0.05, nsteps // K)
+    say(f"case: adjoint fp64 {collision} solids={solids} N={nsteps} ckpt={ckpt}")
+    grid = OP.Grid(wl.nx, wl.ny, wl.nz, wl.periodic, wl.solid)
+    prm = OP.OracleParams.from_workload(wl.params, collision)
+    Lo, dphio, dMo, dso, tro = AD.loss_and_gradients(grid, prm, wl.phi0, wl.u0, wl.pstar0, nsteps,
+                                                     K, 12.0, target)
+    Lg, dphig, dMg, dsg, trg = _gpu_grads(wl, "fp64", collision, nsteps, K, 12.0, target, ckpt)
+    e_tr = (trg - tro).abs().max().item()
+    e_phi = (dphig - dphio).abs().max().item() / dphio.abs().max().item()
+    # conditioning floor of dL/dphi0: the oracle's own gradient under a 1e-15
+    # relative perturbation of phi0 (the regularised normal n = grad phi /
+    # |grad phi|_eps amplifies rounding where |grad phi| is tiny)
+    rng2 = np.random.default_rng(1)
+    phi1 = wl.phi0 * (1 + 1e-15 * rng2.standard_normal(wl.phi0.shape))
+    _, dphi1, _, _, _ = AD.loss_and_gradients(grid, prm, phi1, wl.u0, wl.pstar0, nsteps, K, 12.0,
+                                              target)
+    floor = (dphi1 - dphio).abs().max().item() / dphio.abs().max().item()
+    say(f"  L {Lg:.6e} vs {Lo:.6e}; dM {dMg:.6e} vs {dMo:.6e} ({_rel(dMg, dMo):.1e}); "
+        f"dsigma {dsg:.6e} vs {dso:.6e} ({_rel(dsg, dso):.1e}); dphi0 normwise {e_phi:.1e} "
+        f"(oracle floor {floor:.1e})")
+    assert e_tr <= 1e-12
+    assert _rel(Lg, Lo) <= 1e-10
+    assert _rel(dMg, dMo) <= 1e-10
+    assert _rel(dsg, dso) <= 1e-10
+    assert e_phi <= max(1e-10, 20 * floor)
+
+
+def _config3_target(wl, nsteps, K):
+    """C15: FP64 trace at (1.1 M, 0.9 sigma) plus seeded noise of 1e-3 a0."""
+    from paper_2206_11637_amd.rollout import amplitude_rollout
+    from paper_2206_11637_amd.sim import Simulation
+    sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, "fp64", "mrt", wl.solid, wl.params)
+    dev = sim.device
+    with torch.no_grad():
+        tr = amplitude_rollout(sim, torch.tensor(wl.phi0, device=dev),
+                               torch.tensor(1.1 * wl.params.mobility, dtype=torch.float64),
+                               torch.tensor(0.9 * wl.params.sigma, dtype=torch.float64),
+                               params=wl.params, nsteps=nsteps, sample_every=K, depth=64.0,
+                               u0=wl.u0, pstar0=wl.pstar0).cpu().numpy()
+    rng = np.random.default_rng(W.SEED)
+    return tr + rng.normal(0, 1e-3 * 3.2, tr.shape)
+
+
+def _loss_fp64(wl, target, nsteps, K, M, sigma, phi0=None):
+    from paper_2206_11637_amd.rollout import amplitude_rollout
+    from paper_2206_11637_amd.sim import Simulation
+    sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, "fp64", "mrt", wl.solid, wl.params)
+    dev = sim.device
+    p0 = torch.tensor(wl.phi0 if phi0 is None else phi0, device=dev)
+    with torch.no_grad():
+        tr = amplitude_rollout(sim, p0, torch.tensor(M, dtype=torch.float64),
+                               torch.tensor(sigma, dtype=torch.float64), params=wl.params,
+                               nsteps=nsteps, sample_every=K, depth=64.0, u0=wl.u0,
+                               pstar0=wl.pstar0)
+    return float(((tr.cpu() - torch.as_tensor(target)) ** 2).sum())
+
+
+def test_config3_gradients_match_central_differences_fp64():
+    """64x128x64 capillary wave, 2000 steps, sqrt(N) checkpoints: dL/dM,
+    dL/dsigma and dL/dphi0 (3 seeded directions) against central differences
+    with h = 1e-4 relative, all in FP64."""
+    wl = W.config3()
+    N, K = wl.steps, 10
+    say("case: config3 fp64 gradients vs central differences")
+    target = _config3_target(wl, N, K)
+    stats = {}
+    L, dphi, dM, ds, _ = _gpu_grads(wl, "fp64", "mrt", N, K, 64.0, target, stats=stats)
+    say(f"  L={L:.6e} dM={dM:.6e} dsigma={ds:.6e} checkpoints={stats.get('checkpoints')}")
+    M0, s0 = wl.params.mobility, wl.params.sigma
+    for name, val, grad in (("M", M0, dM), ("sigma", s0, ds)):
+        hstep = 1e-4 * val
+        args_p = (M0 + hstep, s0) if name == "M" else (M0, s0 + hstep)
+        args_m = (M0 - hstep, s0) if name == "M" else (M0, s0 - hstep)
+        fd = (_loss_fp64(wl, target, N, K, *args_p) - _loss_fp64(wl, target, N, K, *args_m)) / (2 * hstep)
+        say(f"  d{name}: adjoint {grad:.8e} fd {fd:.8e} rel {_rel(grad, fd):.2e}")
+        assert _rel(grad, fd) <= 1e-4
+    rng = np.random.default_rng(W.SEED + 1)
+    z, y, x = np.meshgrid(*(np.arange(n) + 0.5 for n in (wl.nz, wl.ny, wl.nx)), indexing="ij")
+    # three seeded directions: a mode that changes the probe's column sum, a
+    # smooth random mode, and a bump on the interface at the probe column
+    kx, ph = rng.integers(1, 3), rng.uniform(0, 2 * np.pi)
+    dirs = [np.cos(2 * np.pi * kx * x / wl.nx + ph) * np.exp(-((y - 64.0) / 8.0) ** 2)]
+    d = np.zeros_like(wl.phi0)
+    for _ in range(3):
+        k3 = rng.integers(1, 3, size=3)
+        p3 = rng.uniform(0, 2 * np.pi, size=3)
+        d += np.cos(2 * np.pi * k3[0] * x / wl.nx + p3[0]) * np.cos(2 * np.pi * k3[1] * y / wl.ny + p3[1]) \
+            * np.cos(2 * np.pi * k3[2] * z / wl.nz + p3[2])
+    dirs.append(d)
+    c = rng.uniform(0, wl.nz)
+    dirs.append(np.exp(-(x ** 2 + (y - 64.0) ** 2 + (z - c) ** 2) / 18.0))
+    for k, d in enumerate(dirs):
+        # phi0 also sets the light-phase density rho_L + phi drho, whose scale is
+        # rho_L / drho ~ 1e-3, so the step is 1e-6 to stay in the linear regime
+        eps = 1e-6 * np.abs(wl.phi0).max()
+        fd = (_loss_fp64(wl, target, N, K, M0, s0, wl.phi0 + eps * d) -
+              _loss_fp64(wl, target, N, K, M0, s0, wl.phi0 - eps * d)) / (2 * eps)
+        ad = float((dphi.numpy() * d.reshape(-1)).sum())
+        # absolute floor for directions nearly orthogonal to the gradient
+        floor = 1e-8 * float(np.linalg.norm(dphi.numpy()) * np.linalg.norm(d))
+        say(f"  dphi0 direction {k}: adjoint {ad:.8e} fd {fd:.8e} rel {_rel(ad, fd):.2e}")
+        assert abs(ad - fd) <= 1e-4 * abs(fd) + floor
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 0.25), ("fp16s", 1.0)])
+def test_reduced_precision_gradients_track_fp64(precision, tol):
+    """FP32 arithmetic (FP32 or FP16 storage) forward + FP32 adjoint with FP64
+    parameter-gradient sums, against the FP64 gradients (errors reported)."""
+    wl = W.config3()
+    N, K = 400, 10
+    say(f"case: config3 {precision} gradients vs fp64 over {N} steps")
+    target = _config3_target(wl, N, K)
+    L64, dphi64, dM64, ds64, _ = _gpu_grads(wl, "fp64", "mrt", N, K, 64.0, target)
+    L, dphi, dM, ds, _ = _gpu_grads(wl, precision, "mrt", N, K, 64.0, target)
+    e_phi = (dphi - dphi64).abs().max().item() / dphi64.abs().max().item()
+    say(f"  {precision}: dM rel {_rel(dM, dM64):.2e} dsigma rel {_rel(ds, ds64):.2e} "
+        f"dphi0 normwise {e_phi:.2e} L rel {_rel(L, L64):.2e}")
+    assert _rel(dM, dM64) <= tol and _rel(ds, ds64) <= tol
