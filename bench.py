@@ -65,6 +65,49 @@ def time_form(wl, precision, steps, warmup, collision="mrt"):
     return out
 
 
+def adjoint_form(wl, precision, nsteps, sample_every, x0, depth, ckpt=None):
+    """Forward (with checkpoints) and backward (with segment recompute) of the
+    differentiable amplitude rollout; wall times, their ratio and peak HBM."""
+    import time as _t
+
+    import torch
+
+    from paper_2206_11637_amd.rollout import amplitude_rollout
+    from paper_2206_11637_amd.sim import Simulation
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, precision, "mrt", wl.solid, wl.params)
+    dev = sim.device
+    phi0 = torch.tensor(wl.phi0, dtype=torch.float64, device=dev, requires_grad=True)
+    M = torch.tensor(wl.params.mobility, dtype=torch.float64, requires_grad=True)
+    sg = torch.tensor(wl.params.sigma, dtype=torch.float64, requires_grad=True)
+    u0 = torch.as_tensor(wl.u0, dtype=torch.float64).to(dev)
+    p0 = torch.as_tensor(wl.pstar0, dtype=torch.float64).to(dev)
+    stats = {}
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    trace = amplitude_rollout(sim, phi0, M, sg, params=wl.params, nsteps=nsteps,
+                              sample_every=sample_every, depth=depth, x0=x0, u0=u0, pstar0=p0,
+                              checkpoint_every=ckpt, stats=stats)
+    loss = (trace ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = _t.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = _t.perf_counter()
+    fwd, bwd = t1 - t0, t2 - t1
+    cells = wl.cells
+    out = dict(steps=nsteps, forward_s=fwd, backward_s=bwd, backward_over_forward=bwd / fwd,
+               forward_mlups=cells * nsteps / fwd / 1e6,
+               backward_mlups=cells * nsteps / bwd / 1e6,
+               checkpoints=stats.get("checkpoints"), checkpoint_every=stats.get("checkpoint_every"),
+               peak_hbm_GB=torch.cuda.max_memory_allocated() / 1e9,
+               dL_dM=float(M.grad), dL_dsigma=float(sg.grad))
+    del sim, phi0, trace, loss
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline():
     """The FP64 oracle on a bounded sample of the same workload (a z-slab of
     the rising-bubble lattice with its walls), timed on the host cores."""
@@ -101,6 +144,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--adj-steps", type=int, default=400,
+                    help="steps of the Taylor-tube reverse-mode leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of 2 GiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU slab "
@@ -112,23 +159,44 @@ def main():
 
     import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        n = 1 << 29   # 2 GiB of float32 read and 2 GiB written per copy
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
+        return
     log("bench: rising bubble 128x512x128 fp32 mrt")
     wl1 = W.config1()
     main_form = time_form(wl1, "fp32", args.steps, args.warmup)
     log(f"  fp32: {main_form['mlups']:.0f} MLUPS")
     forms = {}
+
+    def form(name, fn, *a):
+        log(f"bench: {name}")
+        try:
+            forms[name] = fn(*a)
+        except Exception as e:          # report, keep the headline line
+            forms[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
+
     if not args.no_forms:
-        log("bench: rising bubble fp64")
-        forms["fp64_rising_bubble_128x512x128"] = time_form(wl1, "fp64", max(args.steps // 2, 10),
-                                                            args.warmup)
+        half = max(args.steps // 2, 10)
+        form("fp64_rising_bubble_128x512x128", time_form, wl1, "fp64", half, args.warmup)
         del wl1
-        log("bench: drop impact 384^3 fp32 and fp16 storage")
         wl2 = W.config2()
-        forms["fp32_drop_impact_384^3"] = time_form(wl2, "fp32", max(args.steps // 2, 10),
-                                                    args.warmup)
-        forms["fp16s_drop_impact_384^3"] = time_form(wl2, "fp16s", max(args.steps // 2, 10),
-                                                     args.warmup)
+        form("fp32_drop_impact_384^3", time_form, wl2, "fp32", half, args.warmup)
+        form("fp16s_drop_impact_384^3", time_form, wl2, "fp16s", half, args.warmup)
         del wl2
+        wl3 = W.config3()
+        form("adjoint_capillary_64x128x64_fp32", adjoint_form, wl3, "fp32", wl3.steps, 10, 0, 64.0)
+        del wl3
+        wl4 = W.config4()
+        form("adjoint_taylor_bubble_128x1024x128_fp16s", adjoint_form, wl4, "fp16s",
+             args.adj_steps, 10, 64, 0.0)
+        del wl4
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")

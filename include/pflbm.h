@@ -64,8 +64,9 @@ typedef enum {
   PFLBM_FP64 = 0,        /* FP64 populations, FP64 arithmetic                     */
   PFLBM_FP32 = 1,        /* FP32 populations, FP32 arithmetic                     */
   PFLBM_FP32_FP16S = 2   /* FP32 arithmetic, populations stored as FP16 of
-                            (f_i - s_i) * 2^k; s_i = FP16-rounded w_i for h,
-                            0 for g; k per lattice from fp16_scale_log2          */
+                            (f_i - s_i) * 2^k; for h, s_i = w_i phi of the cell
+                            that wrote the value (its phi at that step); for g,
+                            s_i = 0; k per lattice from fp16_scale_log2          */
 } pflbm_precision;
 
 typedef enum { PFLBM_BGK = 0, PFLBM_MRT = 1 } pflbm_collision;
@@ -147,7 +148,8 @@ pflbm_status pflbm_read_populations(pflbm_ctx* ctx, double* d_h, double* d_g);
  * Waits for the stream.  Returns PFLBM_ERR_UNSTABLE if any is NaN/Inf. */
 pflbm_status pflbm_reduce(pflbm_ctx* ctx, double out_host[5]);
 
-/* Bytes of one saved state (populations + phi field, storage precision). */
+/* Bytes of one saved state (populations in storage precision, then the
+ * current and the previous phi field). */
 size_t pflbm_state_bytes(const pflbm_ctx* ctx);
 
 /* Copies the state to / from d_buf (device-to-device, asynchronous).  The

@@ -326,6 +326,7 @@ struct AdjArgs {
   const S* ph;
   const S* pg;
   const R* pphi;
+  const R* pphi_prev;   // phi^{n-1}: writers of the level-n populations (FP16 shifts)
   const unsigned char* mask;
   // adjoint of level n+1 (natural layout) and of level n
   const R* lh_in;
@@ -348,19 +349,23 @@ __global__ __launch_bounds__(256) void k_adj_cell(AdjArgs<S> a) {
   R* tile = reinterpret_cast<R*>(smem_raw);
   __shared__ double red[4][2];
   const Geom& G = a.geo;
+  const int TX = G.bx + 2, TY = G.by + 2;
+  R* tile_prev = tile + TX * TY * 3;
   const TileCoord t = tile_of_block(G);
   load_phi_tile<R, MASK>(tile, a.pphi, a.mask, G, t);
+  if (Store<S>::kShift) load_phi_tile<R, MASK>(tile_prev, a.pphi_prev, a.mask, G, t);
   __syncthreads();
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
-  const int TX = G.bx + 2, TY = G.by + 2;
   double acc0 = 0.0, acc1 = 0.0;
   if (x < G.nx && y < G.ny && tile[(TY + ly + 1) * TX + lx + 1] != sentinel<R>()) {
     const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
     const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
     const Nbhd nb = make_nbhd(x, y, z, G);
+    R phw[Q_H];
+    if (Store<S>::kShift) writer_phi_tile(tile_prev, TX, TY, lx, ly, walls, phw);
     R h[Q_H], g[Q_G];
-    load_pops<S, ODD>(a.ph, a.pg, G.N, idx, nb, walls, a.cd, h, g);
+    load_pops<S, ODD>(a.ph, a.pg, G.N, idx, nb, walls, a.cd, phw, h, g);
     R Gx, Gy, Gz, lap;
     stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
     // transposed streaming: Lambda of the slot each post-collision value went to

@@ -3,7 +3,8 @@
 // Data layout in HBM (all structure-of-arrays, x fastest):
 //   h[i * N + idx], i < 15       phase-field populations (storage type S)
 //   g[i * N + idx], i < 27       hydrodynamic populations
-//   phi[2][N]                    phase field, double-buffered (compute type R)
+//   phi[2][N]                    phase field, double-buffered (compute type R):
+//                                phi^n (stencil source) and phi^{n-1}
 //   mask[N]                      optional solids (1 = solid)
 //
 // Streaming is the in-place AA pattern (one population buffer per lattice):
@@ -44,24 +45,31 @@ struct Geom {
 };
 
 // ---- storage codecs -------------------------------------------------------
+// ld/st take the shift s and the scale: stored = (f - s) * 2^k.  FP64 and
+// FP32 store f itself.  FP16 storage shifts every h population by w_i times
+// the phase field of the cell that wrote it (phi^n of the writer, which the
+// reader finds in the previous phi buffer), so both pure phases store values
+// near zero; g is stored unshifted (it is small in the p* gauge).
 template <typename S>
 struct Store;
 template <>
 struct Store<double> {
   using R = double;
+  static constexpr bool kShift = false;
   __device__ static R ld(const double* p, R, R) { return *p; }
   __device__ static void st(double* p, R v, R, R) { *p = v; }
 };
 template <>
 struct Store<float> {
   using R = float;
+  static constexpr bool kShift = false;
   __device__ static R ld(const float* p, R, R) { return *p; }
   __device__ static void st(float* p, R v, R, R) { *p = v; }
 };
-// FP16 storage of (f - shift) * 2^k, decoded exactly into FP32
 template <>
 struct Store<_Float16> {
   using R = float;
+  static constexpr bool kShift = true;
   __device__ static R ld(const _Float16* p, R shift, R inv_scale) {
     return static_cast<float>(*p) * inv_scale + shift;
   }
@@ -72,7 +80,6 @@ struct Store<_Float16> {
 
 template <typename R>
 struct Codec {
-  R sh_h[Q_H];            // shifts of h (0 unless FP16 storage)
   R scale_h, inv_scale_h, scale_g, inv_scale_g;
 };
 
@@ -196,13 +203,18 @@ __device__ __forceinline__ void stencil(const R* tile, int TX, int TY, int lx, i
 }
 
 // ---- population access (AA pattern) --------------------------------------
+// Population i arriving at cell x was written by x - c_i, or by x itself when
+// x - c_i is a wall or solid (bounce-back); this holds for both parities.
+// phw[i] is the phase field of that writer (only used by FP16 storage).
 template <typename S, bool ODD>
 __device__ __forceinline__ void load_pops(const S* __restrict__ H, const S* __restrict__ Gp,
                                           long long N, unsigned idx, const Nbhd& nb,
                                           unsigned walls, const Codec<typename Store<S>::R>& cd,
+                                          const typename Store<S>::R (&phw)[Q_H],
                                           typename Store<S>::R (&h)[Q_H],
                                           typename Store<S>::R (&g)[Q_G]) {
   using St = Store<S>;
+  using R = typename St::R;
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
     int pop = i;
@@ -214,7 +226,7 @@ __device__ __forceinline__ void load_pops(const S* __restrict__ H, const S* __re
         cell = nb.at(-d.x, -d.y, -d.z);
       }
     }
-    h[i] = St::ld(slot(H, N, pop, cell), cd.sh_h[i], cd.inv_scale_h);
+    h[i] = St::ld(slot(H, N, pop, cell), St::kShift ? R(wh(i)) * phw[i] : R(0), cd.inv_scale_h);
   }
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) {
@@ -227,17 +239,21 @@ __device__ __forceinline__ void load_pops(const S* __restrict__ H, const S* __re
         cell = nb.at(-d.x, -d.y, -d.z);
       }
     }
-    g[i] = St::ld(slot(Gp, N, pop, cell), typename Store<S>::R(0), cd.inv_scale_g);
+    g[i] = St::ld(slot(Gp, N, pop, cell), R(0), cd.inv_scale_g);
   }
 }
 
+// phi_self: the writer's own phi^n (the field value, bit-identical to what
+// the readers of the next step look up).
 template <typename S, bool ODD>
 __device__ __forceinline__ void store_pops(S* __restrict__ H, S* __restrict__ Gp, long long N,
                                            unsigned idx, const Nbhd& nb, unsigned walls,
                                            const Codec<typename Store<S>::R>& cd,
+                                           typename Store<S>::R phi_self,
                                            const typename Store<S>::R (&h)[Q_H],
                                            const typename Store<S>::R (&g)[Q_G]) {
   using St = Store<S>;
+  using R = typename St::R;
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
     int pop = opp(i);
@@ -249,7 +265,7 @@ __device__ __forceinline__ void store_pops(S* __restrict__ H, S* __restrict__ Gp
         cell = nb.at(d.x, d.y, d.z);
       }
     }
-    St::st(slot(H, N, pop, cell), h[i], cd.sh_h[i], cd.scale_h);
+    St::st(slot(H, N, pop, cell), h[i], St::kShift ? R(wh(i)) * phi_self : R(0), cd.scale_h);
   }
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) {
@@ -262,7 +278,33 @@ __device__ __forceinline__ void store_pops(S* __restrict__ H, S* __restrict__ Gp
         cell = nb.at(d.x, d.y, d.z);
       }
     }
-    St::st(slot(Gp, N, pop, cell), g[i], typename Store<S>::R(0), cd.scale_g);
+    St::st(slot(Gp, N, pop, cell), g[i], R(0), cd.scale_g);
+  }
+}
+
+// Writer phase fields from an LDS tile (3 planes + halo) of phi^{n-1}.
+template <typename R>
+__device__ __forceinline__ void writer_phi_tile(const R* tp, int TX, int TY, int lx, int ly,
+                                                unsigned walls, R (&phw)[Q_H]) {
+  const R self = tp[(TY + ly + 1) * TX + lx + 1];
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    const Dir d = ch(i);
+    phw[i] = (walls & (1u << nb27(-d.x, -d.y, -d.z)))
+                 ? self
+                 : tp[((1 - d.z) * TY + (ly + 1 - d.y)) * TX + (lx + 1 - d.x)];
+  }
+}
+
+// Writer phase fields read directly from a phi buffer.
+template <typename R>
+__device__ __forceinline__ void writer_phi_direct(const R* __restrict__ phi, unsigned idx,
+                                                  const Nbhd& nb, unsigned walls, R (&phw)[Q_H]) {
+  const R self = phi[idx];
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    const Dir d = ch(i);
+    phw[i] = (walls & (1u << nb27(-d.x, -d.y, -d.z))) ? self : phi[nb.at(-d.x, -d.y, -d.z)];
   }
 }
 
@@ -272,6 +314,7 @@ struct CellArgs {
   S* h;
   S* g;
   const R* phi;              // phi^n (stencil source)
+  const R* phi_prev;         // phi^{n-1} (writers of the populations read now)
   const unsigned char* mask;
   Geom geo;
   Phys<R> P;
@@ -299,13 +342,15 @@ void k_cell(CellArgs<S> a) {
   extern __shared__ unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   const Geom& G = a.geo;
+  const int TX = G.bx + 2, TY = G.by + 2;
+  R* tile_prev = tile + TX * TY * 3;          // only with FP16 storage
   const TileCoord t = tile_of_block(G);
   load_phi_tile<R, MASK>(tile, a.phi, a.mask, G, t);
+  if (Store<S>::kShift) load_phi_tile<R, MASK>(tile_prev, a.phi_prev, a.mask, G, t);
   __syncthreads();
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
   if (x >= G.nx || y >= G.ny) return;
-  const int TX = G.bx + 2, TY = G.by + 2;
   const long long idx = x + (long long)G.nx * (y + (long long)G.ny * z);
   if (tile[(TY + ly + 1) * TX + lx + 1] == sentinel<R>()) {   // solid cell
     if (MODE == MODE_MOMENTS) {
@@ -317,8 +362,10 @@ void k_cell(CellArgs<S> a) {
   }
   const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
   const Nbhd nb = make_nbhd(x, y, z, G);
+  R phw[Q_H];
+  if (Store<S>::kShift) writer_phi_tile(tile_prev, TX, TY, lx, ly, walls, phw);
   R h[Q_H], g[Q_G];
-  load_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd, h, g);
+  load_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd, phw, h, g);
   R Gx, Gy, Gz, lap;
   stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
   CellState<R> c;
@@ -335,7 +382,8 @@ void k_cell(CellArgs<S> a) {
   }
   collide_g<R, MRT>(g, c, a.P);
   collide_h<R, MRT>(h, c, a.P);
-  store_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd, h, g);
+  store_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd,
+                    tile[(TY + ly + 1) * TX + lx + 1], h, g);
 }
 
 // Neighbour-is-wall bits for the populations of one cell, without LDS
@@ -361,6 +409,7 @@ struct LightArgs {
   const S* h;
   const S* g;
   const unsigned char* mask;
+  const R* phi_writers;  // phase field of the writers of the populations read
   Geom geo;
   Codec<R> cd;
   R* phi_out;          // gather target (compute precision)
@@ -392,8 +441,11 @@ __global__ __launch_bounds__(256) void k_light(LightArgs<S> a) {
         for (int i = 0; i < Q_G; ++i) a.out_g[i * G.N + idx] = 0.0;
       }
     } else {
-      const unsigned walls = ODD ? wall_bits_direct<MASK>(x, y, z, G, a.mask) : 0u;
+      const unsigned walls =
+          (ODD || Store<S>::kShift) ? wall_bits_direct<MASK>(x, y, z, G, a.mask) : 0u;
       const Nbhd nb = make_nbhd(x, y, z, G);
+      R phw[Q_H];
+      if (Store<S>::kShift) writer_phi_direct(a.phi_writers, (unsigned)idx, nb, walls, phw);
       R h[Q_H], g[Q_G];
       if (LM == LM_GATHER) {
         using St = Store<S>;
@@ -408,13 +460,14 @@ __global__ __launch_bounds__(256) void k_light(LightArgs<S> a) {
               cell = nb.at(-d.x, -d.y, -d.z);
             }
           }
-          h[i] = St::ld(slot(a.h, G.N, pop, cell), a.cd.sh_h[i], a.cd.inv_scale_h);
+          h[i] = St::ld(slot(a.h, G.N, pop, cell), St::kShift ? R(wh(i)) * phw[i] : R(0),
+                        a.cd.inv_scale_h);
         }
         const R s = sum_h(h);
         a.phi_out[idx] = s;
         if (a.out_phi64) a.out_phi64[idx] = double(s);
       } else {
-        load_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd, h, g);
+        load_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd, phw, h, g);
         if (LM == LM_READ_POPS) {
 #pragma unroll
           for (int i = 0; i < Q_H; ++i) a.out_h[i * G.N + idx] = double(h[i]);
@@ -494,6 +547,7 @@ struct InitArgs {
   const double* phi0;
   const double* u0;      // may be null
   const double* p0;      // may be null
+  const R* phi_ref;      // R(phi0): the phase field the FP16 shifts refer to
   Geom geo;
   Codec<R> cd;
 };
@@ -514,11 +568,19 @@ __global__ __launch_bounds__(256) void k_init(InitArgs<S> a) {
   if (!solid && a.u0) { ux = R(a.u0[idx]); uy = R(a.u0[G.N + idx]); uz = R(a.u0[2 * G.N + idx]); }
   if (!solid && a.p0) p = R(a.p0[idx]);
   const R base = R(1) - R(1.5) * (ux * ux + uy * uy + uz * uz);
+  // the natural layout is read with the even rule, whose writer of
+  // population i is x - c_i (or x at a wall): shift by that cell's phi0
+  R phw[Q_H];
+  if (St::kShift && !solid) {
+    const unsigned walls = wall_bits_direct<MASK>(x, y, z, G, a.mask);
+    writer_phi_direct(a.phi_ref, (unsigned)idx, make_nbhd(x, y, z, G), walls, phw);
+  }
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
     const R cu = dot(ch(i), ux, uy, uz);
     const R v = R(wh(i)) * phi * (base + cu * (R(3) + R(4.5) * cu));
-    St::st(a.h + (long long)i * G.N + idx, v, a.cd.sh_h[i], a.cd.scale_h);
+    const R sh = (St::kShift && !solid) ? R(wh(i)) * phw[i] : R(0);
+    St::st(a.h + (long long)i * G.N + idx, v, sh, a.cd.scale_h);
   }
   const R baseg = p - R(1.5) * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
@@ -527,6 +589,15 @@ __global__ __launch_bounds__(256) void k_init(InitArgs<S> a) {
     const R v = R(wg(i)) * (baseg + cu * (R(3) + R(4.5) * cu));
     St::st(a.g + (long long)i * G.N + idx, v, R(0), a.cd.scale_g);
   }
+}
+
+// FP64 phi0 -> compute precision (zero in solids)
+template <typename R>
+__global__ __launch_bounds__(256) void k_phi_from_f64(const double* __restrict__ in,
+                                                       const unsigned char* __restrict__ mask,
+                                                       long long N, R* __restrict__ out) {
+  const long long i = blockIdx.x * 256ll + threadIdx.x;
+  if (i < N) out[i] = (mask && mask[i]) ? R(0) : R(in[i]);
 }
 
 // phi (compute precision) -> FP64

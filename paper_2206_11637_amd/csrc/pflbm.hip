@@ -95,13 +95,6 @@ AdjLayout make_adj_layout(const pflbm_desc* d, const Layout& L) {
   return A;
 }
 
-double fp16_round(double v) {
-  if (v == 0.0) return 0.0;
-  int e;
-  const double m = std::frexp(v, &e);            // v = m 2^e, 0.5 <= |m| < 1
-  return std::ldexp(std::nearbyint(std::ldexp(m, 11)), e - 11);
-}
-
 }  // namespace
 
 struct pflbm_ctx {
@@ -166,7 +159,6 @@ template <typename R>
 Codec<R> make_codec(const pflbm_ctx* c) {
   Codec<R> cd;
   const bool f16 = c->d.precision == PFLBM_FP32_FP16S;
-  for (int i = 0; i < Q_H; ++i) cd.sh_h[i] = f16 ? R(fp16_round(wh(i))) : R(0);
   const double kh = f16 ? c->p.fp16_scale_log2[0] : 0.0, kg = f16 ? c->p.fp16_scale_log2[1] : 0.0;
   cd.scale_h = R(std::ldexp(1.0, (int)kh));
   cd.inv_scale_h = R(std::ldexp(1.0, -(int)kh));
@@ -186,7 +178,7 @@ unsigned char* mask_ptr(pflbm_ctx* c) {
 template <typename S, bool MRT, bool ODD, int MODE>
 void launch_cell_m(pflbm_ctx* c, const CellArgs<S>& a) {
   using R = typename Store<S>::R;
-  const size_t sm = (size_t)(c->L.bx + 2) * (c->L.by + 2) * 3 * sizeof(R);
+  const size_t sm = (size_t)(c->L.bx + 2) * (c->L.by + 2) * 3 * sizeof(R) * (Store<S>::kShift ? 2 : 1);
   const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
   if (c->d.has_mask)
     hipLaunchKernelGGL((k_cell<S, MRT, ODD, true, MODE>), grd, blk, sm, c->stream, a);
@@ -224,6 +216,7 @@ CellArgs<S> cell_args(pflbm_ctx* c) {
   a.h = pop_h<S>(c);
   a.g = pop_g<S>(c);
   a.phi = phi_buf<R>(c, c->cur);
+  a.phi_prev = phi_buf<R>(c, c->cur ^ 1);
   a.mask = mask_ptr(c);
   a.geo = make_geom(c);
   a.P = make_phys<R>(c->p);
@@ -239,6 +232,7 @@ LightArgs<S> light_args(pflbm_ctx* c) {
   a.h = pop_h<S>(c);
   a.g = pop_g<S>(c);
   a.mask = mask_ptr(c);
+  a.phi_writers = phi_buf<R>(c, c->cur ^ 1);   // writers of the current state: phi^{n-1}
   a.geo = make_geom(c);
   a.cd = make_codec<R>(c);
   a.phi_out = nullptr;
@@ -247,12 +241,15 @@ LightArgs<S> light_args(pflbm_ctx* c) {
   return a;
 }
 
-// phi^n = sum h with the read rule of the step the counter points at
+// phi = sum h with the read rule of the step the counter points at, into
+// buffer `target`; the populations were written by cells whose phi is in the
+// other buffer
 template <typename S>
 void gather_phi(pflbm_ctx* c, int target) {
   using R = typename Store<S>::R;
   LightArgs<S> a = light_args<S>(c);
   a.phi_out = phi_buf<R>(c, target);
+  a.phi_writers = phi_buf<R>(c, target ^ 1);
   launch_light<S, LM_GATHER>(c, a, c->steps & 1);
 }
 
@@ -314,8 +311,14 @@ pflbm_status do_init(pflbm_ctx* c, const double* phi0, const double* u0, const d
   a.phi0 = phi0;
   a.u0 = u0;
   a.p0 = p0;
+  a.phi_ref = phi_buf<R>(c, 1);
   a.geo = make_geom(c);
   a.cd = make_codec<R>(c);
+  // buffer 1 takes R(phi0): the reference of the FP16 shifts of the initial
+  // populations (it plays phi^{-1}); buffer 0 then receives phi^0 = sum h^0
+  const unsigned nb = (unsigned)((c->L.N + 255) / 256);
+  hipLaunchKernelGGL(k_phi_from_f64<R>, dim3(nb), dim3(256), 0, c->stream, phi0, mask_ptr(c), c->L.N,
+                     phi_buf<R>(c, 1));
   const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
   if (c->d.has_mask) hipLaunchKernelGGL((k_init<S, true>), grd, blk, 0, c->stream, a);
   else hipLaunchKernelGGL((k_init<S, false>), grd, blk, 0, c->stream, a);
@@ -425,7 +428,7 @@ pflbm_status pflbm_create(const pflbm_desc* desc, void* d_workspace, size_t byte
   p.rho_H = 1.0;
   p.rho_L = 1e-3;
   p.s_high = 1.0;
-  p.fp16_scale_log2[0] = 8;
+  p.fp16_scale_log2[0] = 12;
   p.fp16_scale_log2[1] = 12;
   p.normal_eps = 1e-4;
   c->p = p;
@@ -516,7 +519,7 @@ pflbm_status pflbm_reduce(pflbm_ctx* c, double out_host[5]) {
 
 size_t pflbm_state_bytes(const pflbm_ctx* c) {
   if (!c) return 0;
-  return c->L.bytes_h + c->L.bytes_g + c->L.bytes_phi;
+  return c->L.bytes_h + c->L.bytes_g + 2 * c->L.bytes_phi;
 }
 
 pflbm_status pflbm_save_state(pflbm_ctx* c, void* dst) {
@@ -530,6 +533,10 @@ pflbm_status pflbm_save_state(pflbm_ctx* c, void* dst) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(o + c->L.bytes_h + c->L.bytes_g, c->ws + c->L.off_phi[c->cur], c->L.bytes_phi,
                        hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o + c->L.bytes_h + c->L.bytes_g + c->L.bytes_phi,
+                       c->ws + c->L.off_phi[c->cur ^ 1], c->L.bytes_phi, hipMemcpyDeviceToDevice,
+                       c->stream);
   return check_hip(c, e, "pflbm_save_state");
 }
 
@@ -544,6 +551,9 @@ pflbm_status pflbm_load_state(pflbm_ctx* c, const void* src, int64_t step_count)
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->ws + c->L.off_phi[0], o + c->L.bytes_h + c->L.bytes_g, c->L.bytes_phi,
                        hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + c->L.off_phi[1], o + c->L.bytes_h + c->L.bytes_g + c->L.bytes_phi,
+                       c->L.bytes_phi, hipMemcpyDeviceToDevice, c->stream);
   c->cur = 0;
   c->steps = step_count;
   c->initialised = true;

@@ -75,7 +75,7 @@ class Params:
     rho_L: float = 1e-3
     g: tuple = (0.0, 0.0, 0.0)
     s_high: float = 1.0
-    fp16_scale_log2: tuple = (8.0, 12.0)
+    fp16_scale_log2: tuple = (12.0, 12.0)
     normal_eps: float = 1e-4
 
     def copy(self, **kw) -> "Params":
