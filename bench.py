@@ -29,6 +29,12 @@ HBM_PEAK_GBPS = 8000.0
 # phi write of the step's 344 B (FP32) / 688 B (FP64) / 176 B (FP16 storage))
 CELL_KERNEL_BYTES = {"fp64": 42 * 8 * 2 + 8, "fp32": 42 * 4 * 2 + 4, "fp16s": 42 * 2 * 2 + 4}
 STEP_BYTES = {"fp64": 688, "fp32": 344, "fp16s": 176}
+# HBM bytes per launch of k_cell on the rising-bubble lattice from rocprofv3
+# FETCH_SIZE / WRITE_SIZE (mean of even and odd steps), scaled by the factors a
+# plain 2 GiB device copy gives on the same box (2.0 for FETCH_SIZE, 1.0 for
+# WRITE_SIZE); taken for the current kernels (profiles/k_cell_rising_bubble_
+# 128x512x128_hbm_traffic.txt) and to be re-measured whenever k_cell changes
+TRAFFIC = {"fp32": 3.023e9, "fp16s": 1.655e9, "fp64": 5.912e9}
 
 
 def log(msg):
@@ -144,6 +150,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16s", "fp64"],
+                    help="storage/arithmetic form of the headline run (default fp32)")
     ap.add_argument("--adj-steps", type=int, default=400,
                     help="steps of the Taylor-tube reverse-mode leg")
     ap.add_argument("--copy-probe", action="store_true",
@@ -168,10 +176,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
         return
-    log("bench: rising bubble 128x512x128 fp32 mrt")
+    prec = args.precision
+    log(f"bench: rising bubble 128x512x128 {prec} mrt")
     wl1 = W.config1()
-    main_form = time_form(wl1, "fp32", args.steps, args.warmup)
-    log(f"  fp32: {main_form['mlups']:.0f} MLUPS")
+    main_form = time_form(wl1, prec, args.steps, args.warmup)
+    log(f"  {prec}: {main_form['mlups']:.0f} MLUPS")
     forms = {}
 
     def form(name, fn, *a):
@@ -212,17 +221,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64"}[prec],
         "data": "synthetic",
         "config": {"workload": "rising_bubble_128x512x128", "cells": 128 * 512 * 128,
-                   "lattices": "D3Q15+D3Q27", "collision": "mrt", "storage": "fp32",
+                   "lattices": "D3Q15+D3Q27", "collision": "mrt", "storage": prec,
                    "boundaries": "bounce-back on all faces"},
         "roofline": {"bound": "hbm", "achieved": round(main_form["cell_kernel_GBps"], 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(main_form["cell_kernel_frac"], 4), "traffic": None,
+                     "frac": round(main_form["cell_kernel_frac"], 4), "traffic": TRAFFIC.get(prec),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
+                     "algorithmic_bytes_per_launch": CELL_KERNEL_BYTES[prec] * 128 * 512 * 128,
                      "kernel": "k_cell (fused collide-and-stream)",
-                     "bytes_per_cell": CELL_KERNEL_BYTES["fp32"]},
-        "step_effective": {"bytes_per_cell": STEP_BYTES["fp32"],
+                     "bytes_per_cell": CELL_KERNEL_BYTES[prec]},
+        "step_effective": {"bytes_per_cell": STEP_BYTES[prec],
                            "GBps": round(main_form["effective_GBps"], 1),
                            "frac": round(main_form["effective_frac"], 4),
                            "phi_kernel_ms": round(main_form["phi_kernel_ms"], 4),

@@ -370,27 +370,24 @@ __global__ __launch_bounds__(256) void k_adj_cell(AdjArgs<S> a) {
     stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
     // transposed streaming: Lambda of the slot each post-collision value went to
     R lh[Q_H], lg[Q_G];
+    const unsigned NS = (unsigned)(G.N * (long long)sizeof(R));
 #pragma unroll
     for (int i = 0; i < Q_H; ++i) {
       const Dir d = ch(i);
       unsigned cell = idx;
-      int pop = opp(i);
-      if (!(walls & (1u << nb27(d.x, d.y, d.z)))) {
+      unsigned off = pair_off<R>(opp(i), idx, NS);
+      if (i && !(walls & (1u << nb27(d.x, d.y, d.z)))) {
         cell = nb.at(d.x, d.y, d.z);
-        pop = i;
+        off = pair_off<R>(i, cell, NS);
       }
-      lh[i] = *slot(a.lh_in, G.N, pop, cell) + a.aphi_in[cell];
+      lh[i] = *reinterpret_cast<const R*>(pair_base(a.lh_in, G.N, i) + off) + a.aphi_in[cell];
     }
 #pragma unroll
     for (int i = 0; i < Q_G; ++i) {
       const Dir d = cg(i);
-      unsigned cell = idx;
-      int pop = opp(i);
-      if (!(walls & (1u << nb27(d.x, d.y, d.z)))) {
-        cell = nb.at(d.x, d.y, d.z);
-        pop = i;
-      }
-      lg[i] = *slot(a.lg_in, G.N, pop, cell);
+      unsigned off = pair_off<R>(opp(i), idx, NS);
+      if (i && !(walls & (1u << nb27(d.x, d.y, d.z)))) off = pair_off<R>(i, nb.at(d.x, d.y, d.z), NS);
+      lg[i] = *reinterpret_cast<const R*>(pair_base(a.lg_in, G.N, i) + off);
     }
     R lGx, lGy, lGz, lL, lomp, lsig;
     cell_vjp<R, MRT>(h, g, Gx, Gy, Gz, lap, a.P, a.K, lh, lg, lGx, lGy, lGz, lL, lomp, lsig);

@@ -47,6 +47,31 @@ __device__ __forceinline__ R sum_h(const R (&h)[Q_H]) {
   return s;
 }
 
+template <bool G27>
+__device__ __forceinline__ constexpr Dir cdir(int i) { return G27 ? cg(i) : ch(i); }
+template <bool G27>
+__device__ __forceinline__ constexpr double wdir(int i) { return G27 ? wg(i) : wh(i); }
+
+// First and second moments (sum c f, sum c c f) over opposite pairs: the
+// library orders each pair as (i, i + 1) with c_{i+1} = -c_i for odd i, so
+// a pair contributes its difference to odd moments and its sum to even ones.
+template <typename R, bool G27, int Q>
+__device__ __forceinline__ void pair_moments(const R (&f)[Q], R& mx, R& my, R& mz, Sym<R>& P) {
+  mx = my = mz = R(0);
+  P = Sym<R>{R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int k = 1; k < Q; k += 2) {
+    const Dir d = cdir<G27>(k);
+    const R sm = f[k] + f[k + 1], df = f[k] - f[k + 1];
+    if (d.x) { mx += d.x > 0 ? df : -df; P.xx += sm; }
+    if (d.y) { my += d.y > 0 ? df : -df; P.yy += sm; }
+    if (d.z) { mz += d.z > 0 ? df : -df; P.zz += sm; }
+    if (d.x * d.y) P.xy += (d.x * d.y > 0) ? sm : -sm;
+    if (d.x * d.z) P.xz += (d.x * d.z > 0) ? sm : -sm;
+    if (d.y * d.z) P.yz += (d.y * d.z > 0) ? sm : -sm;
+  }
+}
+
 // Cell state after the force prologue (everything the collisions need).
 template <typename R>
 struct CellState {
@@ -72,23 +97,12 @@ __device__ __forceinline__ void prologue(const R (&h)[Q_H], const R (&g)[Q_G], R
   c.nz = Gz * ninv;
   const R mu = P.beta4 * phi * (phi - R(1)) * (phi - R(0.5)) - P.kappa * lap;
 
-  R p = R(0), jx = R(0), jy = R(0), jz = R(0);
-  Sym<R> Pi{R(0), R(0), R(0), R(0), R(0), R(0)};
+  R p = g[0];
 #pragma unroll
-  for (int i = 0; i < Q_G; ++i) {
-    const Dir d = cg(i);
-    const R v = g[i];
-    p += v;
-    if (d.x) jx += d.x > 0 ? v : -v;
-    if (d.y) jy += d.y > 0 ? v : -v;
-    if (d.z) jz += d.z > 0 ? v : -v;
-    if (d.x) Pi.xx += v;
-    if (d.y) Pi.yy += v;
-    if (d.z) Pi.zz += v;
-    if (d.x * d.y) Pi.xy += (d.x * d.y) > 0 ? v : -v;
-    if (d.x * d.z) Pi.xz += (d.x * d.z) > 0 ? v : -v;
-    if (d.y * d.z) Pi.yz += (d.y * d.z) > 0 ? v : -v;
-  }
+  for (int i = 1; i < Q_G; ++i) p += g[i];
+  R jx, jy, jz;
+  Sym<R> Pi;
+  pair_moments<R, true, Q_G>(g, jx, jy, jz, Pi);
   c.p = p;
   c.jx = jx;
   c.jy = jy;
@@ -143,7 +157,9 @@ __device__ __forceinline__ R hermite2(Dir d, const Sym<R>& A) {
   return r;
 }
 
-// S12-S13: hydrodynamic collision in place.
+// S12-S13: hydrodynamic collision in place.  Each opposite pair (i, i+1) is
+// done together: the equilibrium and the projection split into a part even
+// in c (shared) and a part odd in c (sign-flipped); the forcing term is odd.
 template <typename R, bool MRT>
 __device__ __forceinline__ void collide_g(R (&g)[Q_G], const CellState<R>& c, const Phys<R>& P) {
   const R uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
@@ -157,20 +173,33 @@ __device__ __forceinline__ void collide_g(R (&g)[Q_G], const CellState<R>& c, co
   const R p3 = c.p * (R(1) / R(3));
   Sym<R> A2{p3 + c.ux * c.ux - c.Pi.xx, p3 + c.uy * c.uy - c.Pi.yy, p3 + c.uz * c.uz - c.Pi.zz,
             c.ux * c.uy - c.Pi.xy, c.ux * c.uz - c.Pi.xz, c.uy * c.uz - c.Pi.yz};
+  {
+    const R w = R(wg(0));
+    R v = g[0] + shi * (w * base - g[0]);
+    if (MRT) v += dlo * w * R(4.5) * hermite2(cg(0), A2);
+    g[0] = v;
+  }
 #pragma unroll
-  for (int i = 0; i < Q_G; ++i) {
-    const Dir d = cg(i);
-    const R w = R(wg(i));
+  for (int k = 1; k < Q_G; k += 2) {
+    const Dir d = cg(k);
+    const R w = R(wg(k));
     const R cu = dot(d, c.ux, c.uy, c.uz);
-    const R geq = w * (base + cu * (R(3) + R(4.5) * cu));
-    const R force = w * fk * dot(d, c.Fx, c.Fy, c.Fz);
-    R v = g[i] + shi * (geq - g[i]) + force;
-    if (MRT) v += dlo * w * (R(3) * dot(d, a1x, a1y, a1z) + R(4.5) * hermite2(d, A2));
-    g[i] = v;
+    const R ev = w * (base + R(4.5) * cu * cu);
+    const R od = w * R(3) * cu;
+    const R fo = w * fk * dot(d, c.Fx, c.Fy, c.Fz);
+    R pe = R(0), po = R(0);
+    if (MRT) {
+      pe = dlo * w * R(4.5) * hermite2(d, A2);
+      po = dlo * w * R(3) * dot(d, a1x, a1y, a1z);
+    }
+    const R gi = g[k], gj = g[k + 1];
+    g[k] = gi + shi * (ev + od - gi) + fo + pe + po;
+    g[k + 1] = gj + shi * (ev - od - gj) - fo + pe - po;
   }
 }
 
-// S14-S15: phase-field collision in place (needs u from the hydro prologue).
+// S14-S15: phase-field collision in place (needs u from the hydro prologue),
+// in the same pair form.
 template <typename R, bool MRT>
 __device__ __forceinline__ void collide_h(R (&h)[Q_H], const CellState<R>& c, const Phys<R>& P) {
   const R uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
@@ -182,19 +211,9 @@ __device__ __forceinline__ void collide_h(R (&h)[Q_H], const CellState<R>& c, co
   Sym<R> A2{R(0), R(0), R(0), R(0), R(0), R(0)};
   R a1x = R(0), a1y = R(0), a1z = R(0);
   if (MRT) {
-    R jx = R(0), jy = R(0), jz = R(0);
-    Sym<R> Pi{R(0), R(0), R(0), R(0), R(0), R(0)};
-#pragma unroll
-    for (int i = 0; i < Q_H; ++i) {
-      const Dir d = ch(i);
-      const R v = h[i];
-      if (d.x) { jx += d.x > 0 ? v : -v; Pi.xx += v; }
-      if (d.y) { jy += d.y > 0 ? v : -v; Pi.yy += v; }
-      if (d.z) { jz += d.z > 0 ? v : -v; Pi.zz += v; }
-      if (d.x * d.y) Pi.xy += (d.x * d.y > 0) ? v : -v;
-      if (d.x * d.z) Pi.xz += (d.x * d.z > 0) ? v : -v;
-      if (d.y * d.z) Pi.yz += (d.y * d.z > 0) ? v : -v;
-    }
+    R jx, jy, jz;
+    Sym<R> Pi;
+    pair_moments<R, false, Q_H>(h, jx, jy, jz, Pi);
     // moments of h^eq: phi u, phi (I/3 + u u)
     a1x = phi * c.ux - jx;
     a1y = phi * c.uy - jy;
@@ -204,17 +223,29 @@ __device__ __forceinline__ void collide_h(R (&h)[Q_H], const CellState<R>& c, co
                 p3 + phi * c.uz * c.uz - Pi.zz, phi * c.ux * c.uy - Pi.xy,
                 phi * c.ux * c.uz - Pi.xz, phi * c.uy * c.uz - Pi.yz};
   }
-  const R base = R(1) - R(1.5) * uu;
+  const R base = phi * (R(1) - R(1.5) * uu);
+  {
+    const R w = R(wh(0));
+    R v = h[0] + shi * (w * base - h[0]);
+    if (MRT) v += dlo * w * R(4.5) * hermite2(ch(0), A2);
+    h[0] = v;
+  }
 #pragma unroll
-  for (int i = 0; i < Q_H; ++i) {
-    const Dir d = ch(i);
-    const R w = R(wh(i));
+  for (int k = 1; k < Q_H; k += 2) {
+    const Dir d = ch(k);
+    const R w = R(wh(k));
     const R cu = dot(d, c.ux, c.uy, c.uz);
-    const R heq = w * phi * (base + cu * (R(3) + R(4.5) * cu));
-    const R force = w * fk * dot(d, c.nx, c.ny, c.nz);
-    R v = h[i] + shi * (heq - h[i]) + force;
-    if (MRT) v += dlo * w * (R(3) * dot(d, a1x, a1y, a1z) + R(4.5) * hermite2(d, A2));
-    h[i] = v;
+    const R ev = w * (base + R(4.5) * phi * cu * cu);
+    const R od = w * R(3) * phi * cu;
+    const R fo = w * fk * dot(d, c.nx, c.ny, c.nz);
+    R pe = R(0), po = R(0);
+    if (MRT) {
+      pe = dlo * w * R(4.5) * hermite2(d, A2);
+      po = dlo * w * R(3) * dot(d, a1x, a1y, a1z);
+    }
+    const R hi = h[k], hj = h[k + 1];
+    h[k] = hi + shi * (ev + od - hi) + fo + pe + po;
+    h[k + 1] = hj + shi * (ev - od - hj) - fo + pe - po;
   }
 }
 

@@ -33,9 +33,10 @@ bool desc_ok(const pflbm_desc* d) {
   if (d->collision < 0 || d->collision > 1) return false;
   if (d->periodic > 7u) return false;
   const long long N = (long long)d->nx * d->ny * d->nz;
-  // population addressing uses 32-bit byte offsets within each population
-  const long long per_pop = N * (long long)(d->precision == PFLBM_FP64 ? 8 : 4);
-  if (per_pop >= (1ll << 32)) return false;
+  // population addressing uses 32-bit byte offsets within each opposite pair
+  // of populations (and within the FP32/FP64 adjoint arrays of one population)
+  const long long per_pair = 2 * N * (long long)(d->precision == PFLBM_FP64 ? 8 : 4);
+  if (per_pair >= (1ll << 32)) return false;
   return true;
 }
 
@@ -49,7 +50,10 @@ struct Layout {
 
 Layout make_layout(const pflbm_desc* d) {
   Layout L{};
-  L.bx = d->nx > 32 ? 64 : (d->nx > 16 ? 32 : 16);
+#ifndef PFLBM_TILE_X
+#define PFLBM_TILE_X 64
+#endif
+  L.bx = d->nx > 32 ? PFLBM_TILE_X : (d->nx > 16 ? 32 : 16);
   L.by = 256 / L.bx;
   L.tiles_x = (d->nx + L.bx - 1) / L.bx;
   L.tiles_y = (d->ny + L.by - 1) / L.by;
