@@ -114,6 +114,45 @@ def adjoint_form(wl, precision, nsteps, sample_every, x0, depth, ckpt=None):
     return out
 
 
+def precision_errors(wl, checkpoints=(100, 500)):
+    """FP32 and FP16-storage forms against the FP64 path (which matches the FP64
+    oracle to ~1e-14): max|dphi|, max|du| / max|u|, mass drift at each checkpoint."""
+    import torch
+
+    from paper_2206_11637_amd.sim import from_workload
+    ref = {}
+    sim = from_workload(wl, precision="fp64")
+    m0 = sim.reduce()[0]
+    n = 0
+    for k in checkpoints:
+        sim.step(k - n)
+        n = k
+        phi, u, _ = sim.moments()
+        ref[k] = (phi, u, (sim.reduce()[0] - m0) / m0)
+    del sim
+    out = {}
+    for prec in ("fp32", "fp16s"):
+        sim = from_workload(wl, precision=prec)
+        m0 = sim.reduce()[0]
+        n = 0
+        for k in checkpoints:
+            sim.step(k - n)
+            n = k
+            phi, u, _ = sim.moments()
+            pr, ur, dr = ref[k]
+            out[f"{prec}_step{k}"] = {
+                "max_abs_dphi": (phi - pr).abs().max().item(),
+                "max_abs_du_over_max_u": ((u - ur).abs().max() / ur.abs().max()).item(),
+                "mass_drift": (sim.reduce()[0] - m0) / m0,
+                "fp64_mass_drift": dr}
+            del phi, u
+        del sim
+        torch.cuda.empty_cache()
+    del ref
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline():
     """The FP64 oracle on a bounded sample of the same workload (a z-slab of
     the rising-bubble lattice with its walls), timed on the host cores."""
@@ -198,6 +237,7 @@ def main():
         wl2 = W.config2()
         form("fp32_drop_impact_384^3", time_form, wl2, "fp32", half, args.warmup)
         form("fp16s_drop_impact_384^3", time_form, wl2, "fp16s", half, args.warmup)
+        form("precision_errors_drop_impact_384^3", precision_errors, wl2)
         del wl2
         wl3 = W.config3()
         form("adjoint_capillary_64x128x64_fp32", adjoint_form, wl3, "fp32", wl3.steps, 10, 0, 64.0)
@@ -239,9 +279,16 @@ def main():
                            "phi_kernel_ms": round(main_form["phi_kernel_ms"], 4),
                            "cell_kernel_ms": round(main_form["cell_kernel_ms"], 4)},
         "cpu_baseline": cpu,
-        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                  for k, v in forms.items()},
+        "forms": forms,
     }
+    def _round(v):
+        if isinstance(v, float):
+            return float(f"{v:.5g}")
+        if isinstance(v, dict):
+            return {k: _round(x) for k, x in v.items()}
+        return v
+
+    line["forms"] = _round(line["forms"])
     print(json.dumps(line), flush=True)
 
 

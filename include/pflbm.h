@@ -128,8 +128,15 @@ pflbm_status pflbm_init_equilibrium(pflbm_ctx* ctx, const double* d_phi0,
                                     const double* d_u0, const double* d_pstar0);
 
 /* Advances nsteps >= 0 time steps (collide + stream of h and g, then the phi
- * update), asynchronously. */
+ * update), asynchronously.  With a check interval K > 0 (pflbm_set_check_interval)
+ * it also reduces sum(phi) and sum(p*) in FP64 every K steps, waits for that
+ * result, and stops with PFLBM_ERR_UNSTABLE at the first non-finite one; the
+ * step count then names the step after which it was detected. */
 pflbm_status pflbm_step(pflbm_ctx* ctx, int64_t nsteps);
+
+/* Sets the stability check interval K of pflbm_step (0 = never, the
+ * default; each check costs one reduction and one host round trip). */
+pflbm_status pflbm_set_check_interval(pflbm_ctx* ctx, int64_t every);
 
 /* Cell moments of the current state as FP64: phi [N], u [3][N] (the
  * force-corrected velocity u = j + F/(2 rho)), p* [N]; zero in solids.  Any
@@ -157,6 +164,12 @@ size_t pflbm_state_bytes(const pflbm_ctx* ctx);
  * selects the in-place streaming layout). */
 pflbm_status pflbm_save_state(pflbm_ctx* ctx, void* d_dst);
 pflbm_status pflbm_load_state(pflbm_ctx* ctx, const void* d_src, int64_t step_count);
+
+/* One time step from a saved state of level n (d_src, as written by
+ * pflbm_save_state) into another, non-overlapping buffer of the same size
+ * (d_dst, level n + 1), without touching the context's own state; used to
+ * recompute checkpoint segments without copies.  Asynchronous. */
+pflbm_status pflbm_step_states(pflbm_ctx* ctx, const void* d_src, void* d_dst, int64_t n);
 
 /* Steps taken since the last init or load. */
 int64_t pflbm_step_count(const pflbm_ctx* ctx);

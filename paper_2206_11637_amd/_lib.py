@@ -35,6 +35,7 @@ SIGNATURES = {
     "pflbm_set_mask": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pflbm_init_equilibrium": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pflbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "pflbm_set_check_interval": (C.c_int, [C.c_void_p, C.c_int64]),
     "pflbm_read_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pflbm_read_phi": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pflbm_read_populations": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -42,6 +43,7 @@ SIGNATURES = {
     "pflbm_state_bytes": (C.c_size_t, [C.c_void_p]),
     "pflbm_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pflbm_load_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "pflbm_step_states": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "pflbm_step_count": (C.c_int64, [C.c_void_p]),
     "pflbm_profile_step": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double)]),
     "pflbm_sync": (C.c_int, [C.c_void_p]),

@@ -76,20 +76,12 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   const R nx = Gx * rn, ny = Gy * rn, nz = Gz * rn;
   const R p3c = phi * (phi - R(1)) * (phi - R(0.5));
   const R mu = P.beta4 * p3c - P.kappa * lap;
-  R p = R(0), jx = R(0), jy = R(0), jz = R(0);
-  Sym<R> Pi{R(0), R(0), R(0), R(0), R(0), R(0)};
+  R p = g[0];
 #pragma unroll
-  for (int i = 0; i < Q_G; ++i) {
-    const Dir d = cg(i);
-    const R v = g[i];
-    p += v;
-    if (d.x) { jx += d.x > 0 ? v : -v; Pi.xx += v; }
-    if (d.y) { jy += d.y > 0 ? v : -v; Pi.yy += v; }
-    if (d.z) { jz += d.z > 0 ? v : -v; Pi.zz += v; }
-    if (d.x * d.y) Pi.xy += (d.x * d.y > 0) ? v : -v;
-    if (d.x * d.z) Pi.xz += (d.x * d.z > 0) ? v : -v;
-    if (d.y * d.z) Pi.yz += (d.y * d.z > 0) ? v : -v;
-  }
+  for (int i = 1; i < Q_G; ++i) p += g[i];
+  R jx, jy, jz;
+  Sym<R> Pi;
+  pair_moments<R, true, Q_G>(g, jx, jy, jz, Pi);
   const R third = R(1) / R(3);
   const R cgr = mu - p * third * P.drho;
   const R F0x = cgr * Gx + rho * P.gx, F0y = cgr * Gy + rho * P.gy, F0z = cgr * Gz + rho * P.gz;
@@ -114,19 +106,9 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   R a1hx = R(0), a1hy = R(0), a1hz = R(0);
   Sym<R> A2h{R(0), R(0), R(0), R(0), R(0), R(0)};
   if (MRT) {
-    R hx = R(0), hy = R(0), hz = R(0);
-    Sym<R> Ph{R(0), R(0), R(0), R(0), R(0), R(0)};
-#pragma unroll
-    for (int i = 0; i < Q_H; ++i) {
-      const Dir d = ch(i);
-      const R v = h[i];
-      if (d.x) { hx += d.x > 0 ? v : -v; Ph.xx += v; }
-      if (d.y) { hy += d.y > 0 ? v : -v; Ph.yy += v; }
-      if (d.z) { hz += d.z > 0 ? v : -v; Ph.zz += v; }
-      if (d.x * d.y) Ph.xy += (d.x * d.y > 0) ? v : -v;
-      if (d.x * d.z) Ph.xz += (d.x * d.z > 0) ? v : -v;
-      if (d.y * d.z) Ph.yz += (d.y * d.z > 0) ? v : -v;
-    }
+    R hx, hy, hz;
+    Sym<R> Ph;
+    pair_moments<R, false, Q_H>(h, hx, hy, hz, Ph);
     a1hx = phi * ux - hx;
     a1hy = phi * uy - hy;
     a1hz = phi * uz - hz;
@@ -141,39 +123,53 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   R la1hx = R(0), la1hy = R(0), la1hz = R(0);
   Sym<R> lA2h{R(0), R(0), R(0), R(0), R(0), R(0)};
   R lomp = R(0);
+  {  // rest population: c = 0
+    const R w = R(wh(0));
+    const R lam = lh[0];
+    l_phi += sh * lam * w * hbase;
+    l_hbase += sh * lam * w * phi;
+    if (MRT) {
+      hermite2_grad(ch(0), R(4.5) * dloh * lam * w, lA2h);
+      lomp += lam * w * R(4.5) * hermite2(ch(0), A2h);
+    } else {
+      lomp += lam * (w * phi * hbase - h[0]);
+    }
+  }
+  // opposite pairs (k, k+1): sp/sm are the sum/difference of their adjoints,
+  // E/O the parts of the equilibrium polynomial even/odd in c
 #pragma unroll
-  for (int i = 0; i < Q_H; ++i) {
-    const Dir d = ch(i);
-    const R w = R(wh(i));
-    const R lam = lh[i];
+  for (int k = 1; k < Q_H; k += 2) {
+    const Dir d = ch(k);
+    const R w = R(wh(k));
+    const R la = lh[k], lb = lh[k + 1];
+    const R sp = la + lb, sm = la - lb;
     const R cu = dot(d, ux, uy, uz);
-    const R e = hbase + cu * (R(3) + R(4.5) * cu);
+    const R E = hbase + R(4.5) * cu * cu, O = R(3) * cu;
     const R cn = dot(d, nx, ny, nz);
-    const R lheq = sh * lam;
-    l_phi += lheq * w * e;
-    l_hbase += lheq * w * phi;
-    const R lcu = lheq * w * phi * (R(3) + R(9) * cu);
+    l_phi += sh * w * (sp * E + sm * O);
+    l_hbase += sh * w * phi * sp;
+    const R lcu = sh * w * phi * (R(3) * sm + R(9) * cu * sp);
     if (d.x) lux += d.x > 0 ? lcu : -lcu;
     if (d.y) luy += d.y > 0 ? lcu : -lcu;
     if (d.z) luz += d.z > 0 ? lcu : -lcu;
-    l_fkh += lam * w * cn;
-    const R ln = lam * w * fkh;
+    l_fkh += w * cn * sm;
+    const R ln = w * fkh * sm;
     if (d.x) lnx += d.x > 0 ? ln : -ln;
     if (d.y) lny += d.y > 0 ? ln : -ln;
     if (d.z) lnz += d.z > 0 ? ln : -ln;
     if (MRT) {
-      const R proj = w * (R(3) * dot(d, a1hx, a1hy, a1hz) + R(4.5) * hermite2(d, A2h));
-      const R lproj = dloh * lam * w;
-      const R l3 = R(3) * lproj;
+      const R PO = w * R(3) * dot(d, a1hx, a1hy, a1hz);
+      const R PE = w * R(4.5) * hermite2(d, A2h);
+      const R l3 = R(3) * dloh * w * sm;
       if (d.x) la1hx += d.x > 0 ? l3 : -l3;
       if (d.y) la1hy += d.y > 0 ? l3 : -l3;
       if (d.z) la1hz += d.z > 0 ? l3 : -l3;
-      hermite2_grad(d, R(4.5) * lproj, lA2h);
-      lomp += lam * proj;
+      hermite2_grad(d, R(4.5) * dloh * w * sp, lA2h);
+      lomp += sp * PE + sm * PO;
     } else {
-      lomp += lam * (w * phi * e - h[i]);
+      lomp += la * (w * phi * (E + O) - h[k]) + lb * (w * phi * (E - O) - h[k + 1]);
     }
-    lomp -= lam * R(0.5) * theta * w * cn;
+    lomp -= R(0.5) * theta * w * cn * sm;
   }
   const R l_theta = (R(1) - R(0.5) * omp) * l_fkh;
   R lhjx = R(0), lhjy = R(0), lhjz = R(0);
@@ -203,34 +199,46 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   R l_base = R(0), l_fk = R(0), lFx = R(0), lFy = R(0), lFz = R(0), lom = R(0);
   R la1x = R(0), la1y = R(0), la1z = R(0);
   Sym<R> lA2{R(0), R(0), R(0), R(0), R(0), R(0)};
+  {  // rest population
+    const R w = R(wg(0));
+    const R lam = lg[0];
+    l_base += s * lam * w;
+    if (MRT) {
+      hermite2_grad(cg(0), R(4.5) * dlo * lam * w, lA2);
+      lom += lam * w * R(4.5) * hermite2(cg(0), A2);
+    } else {
+      lom += lam * (w * base - g[0]);
+    }
+  }
 #pragma unroll
-  for (int i = 0; i < Q_G; ++i) {
-    const Dir d = cg(i);
-    const R w = R(wg(i));
-    const R lam = lg[i];
+  for (int k = 1; k < Q_G; k += 2) {
+    const Dir d = cg(k);
+    const R w = R(wg(k));
+    const R la = lg[k], lb = lg[k + 1];
+    const R sp = la + lb, sm = la - lb;
     const R cu = dot(d, ux, uy, uz);
-    const R lgeq = s * lam * w;
-    l_base += lgeq;
-    const R lcu = lgeq * (R(3) + R(9) * cu);
+    l_base += s * w * sp;
+    const R lcu = s * w * (R(3) * sm + R(9) * cu * sp);
     if (d.x) lux += d.x > 0 ? lcu : -lcu;
     if (d.y) luy += d.y > 0 ? lcu : -lcu;
     if (d.z) luz += d.z > 0 ? lcu : -lcu;
-    l_fk += lam * w * dot(d, Fx, Fy, Fz);
-    const R lf = lam * w * fk;
+    l_fk += w * dot(d, Fx, Fy, Fz) * sm;
+    const R lf = w * fk * sm;
     if (d.x) lFx += d.x > 0 ? lf : -lf;
     if (d.y) lFy += d.y > 0 ? lf : -lf;
     if (d.z) lFz += d.z > 0 ? lf : -lf;
     if (MRT) {
-      const R proj = w * (R(3) * dot(d, a1x, a1y, a1z) + R(4.5) * hermite2(d, A2));
-      const R lproj = dlo * lam * w;
-      const R l3 = R(3) * lproj;
+      const R PO = w * R(3) * dot(d, a1x, a1y, a1z);
+      const R PE = w * R(4.5) * hermite2(d, A2);
+      const R l3 = R(3) * dlo * w * sm;
       if (d.x) la1x += d.x > 0 ? l3 : -l3;
       if (d.y) la1y += d.y > 0 ? l3 : -l3;
       if (d.z) la1z += d.z > 0 ? l3 : -l3;
-      hermite2_grad(d, R(4.5) * lproj, lA2);
-      lom += lam * proj;
+      hermite2_grad(d, R(4.5) * dlo * w * sp, lA2);
+      lom += sp * PE + sm * PO;
     } else {
-      lom += lam * (w * (base + cu * (R(3) + R(4.5) * cu)) - g[i]);
+      const R E = base + R(4.5) * cu * cu, O = R(3) * cu;
+      lom += la * (w * (E + O) - g[k]) + lb * (w * (E - O) - g[k + 1]);
     }
   }
   lom += l_fk * (-R(1.5) / rho);
@@ -304,17 +312,25 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   l_omphi = lomp;
 
   // ---------------- adjoints of the pre-collision populations ----------------
+  lg[0] = (R(1) - s) * lg[0] + l_p;
 #pragma unroll
-  for (int i = 0; i < Q_G; ++i) {
-    const Dir d = cg(i);
-    lg[i] = (R(1) - s) * lg[i] + l_p + dot(d, ljx, ljy, ljz) + second_moment_t(d, lPi);
+  for (int k = 1; k < Q_G; k += 2) {
+    const Dir d = cg(k);
+    const R ev = l_p + second_moment_t(d, lPi), od = dot(d, ljx, ljy, ljz);
+    lg[k] = (R(1) - s) * lg[k] + ev + od;
+    lg[k + 1] = (R(1) - s) * lg[k + 1] + ev - od;
   }
+  lh[0] = (R(1) - sh) * lh[0] + l_phi;
 #pragma unroll
-  for (int i = 0; i < Q_H; ++i) {
-    const Dir d = ch(i);
-    R v = (R(1) - sh) * lh[i] + l_phi;
-    if (MRT) v += dot(d, lhjx, lhjy, lhjz) + second_moment_t(d, lPh);
-    lh[i] = v;
+  for (int k = 1; k < Q_H; k += 2) {
+    const Dir d = ch(k);
+    R ev = l_phi, od = R(0);
+    if (MRT) {
+      ev += second_moment_t(d, lPh);
+      od = dot(d, lhjx, lhjy, lhjz);
+    }
+    lh[k] = (R(1) - sh) * lh[k] + ev + od;
+    lh[k + 1] = (R(1) - sh) * lh[k + 1] + ev - od;
   }
 }
 
@@ -343,7 +359,8 @@ struct AdjArgs {
 };
 
 template <typename S, bool MRT, bool ODD, bool MASK>
-__global__ __launch_bounds__(256) void k_adj_cell(AdjArgs<S> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<S>::value)))
+void k_adj_cell(AdjArgs<S> a) {
   using R = typename Store<S>::R;
   extern __shared__ unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);

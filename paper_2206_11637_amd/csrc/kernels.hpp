@@ -358,7 +358,9 @@ __device__ __forceinline__ void writer_phi_direct(const R* __restrict__ phi, uns
 template <typename S>
 struct CellArgs {
   using R = typename Store<S>::R;
-  S* h;
+  const S* h_in;             // populations read (== h, g for the in-place step)
+  const S* g_in;
+  S* h;                      // populations written
   S* g;
   const R* phi;              // phi^n (stencil source)
   const R* phi_prev;         // phi^{n-1} (writers of the populations read now)
@@ -412,7 +414,7 @@ void k_cell(CellArgs<S> a) {
   R phw[Q_H];
   if (Store<S>::kShift) writer_phi_tile(tile_prev, TX, TY, lx, ly, walls, phw);
   R h[Q_H], g[Q_G];
-  load_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd, phw, h, g);
+  load_pops<S, ODD>(a.h_in, a.g_in, G.N, (unsigned)idx, nb, walls, a.cd, phw, h, g);
   R Gx, Gy, Gz, lap;
   stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
   CellState<R> c;

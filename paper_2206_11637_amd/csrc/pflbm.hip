@@ -109,6 +109,7 @@ struct pflbm_ctx {
   char* ws;
   int cur = 0;
   int64_t steps = 0;
+  int64_t check_every = 0;
   bool initialised = false;
   bool mask_set = false;
   // adjoint
@@ -219,6 +220,8 @@ CellArgs<S> cell_args(pflbm_ctx* c) {
   CellArgs<S> a;
   a.h = pop_h<S>(c);
   a.g = pop_g<S>(c);
+  a.h_in = a.h;
+  a.g_in = a.g;
   a.phi = phi_buf<R>(c, c->cur);
   a.phi_prev = phi_buf<R>(c, c->cur ^ 1);
   a.mask = mask_ptr(c);
@@ -258,6 +261,9 @@ void gather_phi(pflbm_ctx* c, int target) {
 }
 
 template <typename S>
+pflbm_status do_reduce(pflbm_ctx* c, double* out_host);
+
+template <typename S>
 pflbm_status do_steps(pflbm_ctx* c, int64_t n) {
   for (int64_t s = 0; s < n; ++s) {
     CellArgs<S> a = cell_args<S>(c);
@@ -265,8 +271,43 @@ pflbm_status do_steps(pflbm_ctx* c, int64_t n) {
     c->steps += 1;
     gather_phi<S>(c, c->cur ^ 1);
     c->cur ^= 1;
+    if (c->check_every > 0 && c->steps % c->check_every == 0) {
+      double r[5];
+      const pflbm_status st = do_reduce<S>(c, r);
+      if (st == PFLBM_ERR_UNSTABLE)
+        return fail(c, st, "non-finite sum(phi) or sum(p*) after step " + std::to_string(c->steps));
+      if (st) return st;
+    }
   }
   return check_hip(c, hipGetLastError(), "pflbm_step");
+}
+
+// One step from a saved state (level n) into another saved-state buffer
+// (level n + 1), leaving the context's own state untouched.  Out of place is
+// valid for the AA pattern because each step writes every slot exactly once.
+template <typename S>
+pflbm_status do_step_states(pflbm_ctx* c, const void* src, void* dst, int64_t n) {
+  using R = typename Store<S>::R;
+  const char* s = static_cast<const char*>(src);
+  char* d = static_cast<char*>(dst);
+  const size_t oh = 0, og = c->L.bytes_h, op = c->L.bytes_h + c->L.bytes_g, oq = op + c->L.bytes_phi;
+  CellArgs<S> a = cell_args<S>(c);
+  a.h_in = reinterpret_cast<const S*>(s + oh);
+  a.g_in = reinterpret_cast<const S*>(s + og);
+  a.h = reinterpret_cast<S*>(d + oh);
+  a.g = reinterpret_cast<S*>(d + og);
+  a.phi = reinterpret_cast<const R*>(s + op);
+  a.phi_prev = reinterpret_cast<const R*>(s + oq);
+  launch_cell<S, MODE_STEP>(c, a, n & 1);
+  LightArgs<S> b = light_args<S>(c);
+  b.h = a.h;
+  b.g = a.g;
+  b.phi_writers = reinterpret_cast<const R*>(s + op);
+  b.phi_out = reinterpret_cast<R*>(d + op);
+  launch_light<S, LM_GATHER>(c, b, (n + 1) & 1);
+  hipError_t e = hipMemcpyAsync(d + oq, s + op, c->L.bytes_phi, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return check_hip(c, e, "pflbm_step_states copy");
+  return check_hip(c, hipGetLastError(), "pflbm_step_states");
 }
 
 template <typename S>
@@ -473,6 +514,13 @@ pflbm_status pflbm_init_equilibrium(pflbm_ctx* c, const double* phi0, const doub
   DISPATCH(c, do_init, c, phi0, u0, p0);
 }
 
+pflbm_status pflbm_set_check_interval(pflbm_ctx* c, int64_t every) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (every < 0) return fail(c, PFLBM_ERR_ARG, "negative check interval");
+  c->check_every = every;
+  return PFLBM_OK;
+}
+
 pflbm_status pflbm_step(pflbm_ctx* c, int64_t n) {
   if (!c) return PFLBM_ERR_ARG;
   if (n < 0) return fail(c, PFLBM_ERR_ARG, "negative step count");
@@ -562,6 +610,13 @@ pflbm_status pflbm_load_state(pflbm_ctx* c, const void* src, int64_t step_count)
   c->steps = step_count;
   c->initialised = true;
   return check_hip(c, e, "pflbm_load_state");
+}
+
+pflbm_status pflbm_step_states(pflbm_ctx* c, const void* src, void* dst, int64_t n) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!src || !dst || src == dst || n < 0) return fail(c, PFLBM_ERR_ARG, "bad state buffers or step index");
+  if (c->d.has_mask && !c->mask_set) return fail(c, PFLBM_ERR_STATE, "mask not set");
+  DISPATCH(c, do_step_states, c, src, dst, n);
 }
 
 int64_t pflbm_step_count(const pflbm_ctx* c) { return c ? c->steps : -1; }

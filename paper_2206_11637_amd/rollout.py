@@ -5,10 +5,11 @@ PFLBMRollout maps (phi0, M, sigma) to the interface-amplitude trace
 (the column-sum elevation probe of the paper's standing-wave tests, sec.
 "Gravity wave" setup).  Its backward runs the adjoint step kernels in reverse
 time, with sqrt(N) checkpointing: the forward keeps every S-th state
-(S ~ sqrt(N)); the backward reloads each checkpoint, recomputes its segment
-of S states into a segment buffer and walks it backwards.  Peak memory is
-about 2 sqrt(N) saved states instead of N.  The forward recompute is
-bit-identical to the original forward (deterministic kernels).
+(S ~ sqrt(N)); the backward recomputes each checkpoint's segment of S states
+out of place (state k+1 written straight from state k into the segment
+buffer, no copies) and walks it backwards.  Peak memory is about 2 sqrt(N)
+saved states instead of N.  The recompute is bit-identical to the original
+forward (deterministic kernels).
 """
 from __future__ import annotations
 
@@ -91,17 +92,19 @@ class PFLBMRollout(torch.autograd.Function):
                 inj[:, :, spec.x0] = grad_trace[level // K - 1] / nz
                 sim.adjoint_inject_phi(inj)
 
-        seg = torch.empty((S, sim.state_bytes()), dtype=torch.uint8, device=sim.device)
+        # segment buffer: slot 0 is the checkpoint itself, slots 1..S-1 are
+        # recomputed out of place from the previous slot (no state copies)
+        seg = torch.empty((max(S - 1, 1), sim.state_bytes()), dtype=torch.uint8, device=sim.device)
         starts = sorted(ckpt)
         for a in reversed(starts):
             b = min(a + S, N)
-            sim.load_state(ckpt[a], a)
-            for n in range(a, b):
-                sim.save_state(seg[n - a])
-                sim.step(1)
+            states = [ckpt[a]]
+            for n in range(a, b - 1):
+                sim.step_states(states[-1], seg[n - a], n)
+                states.append(seg[n - a])
             for n in range(b - 1, a - 1, -1):
                 inject(n + 1)
-                sim.adjoint_step(seg[n - a], n)
+                sim.adjoint_step(states[n - a], n)
         dphi0 = sim.adjoint_init(spec.u0)
         dM, dsig = sim.adjoint_grads()
         spec.stats["segment_states"] = S

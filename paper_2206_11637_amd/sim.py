@@ -102,6 +102,11 @@ class Simulation:
         check(self.lib.pflbm_init_equilibrium(self.ctx, _ptr(phi), _ptr(u), _ptr(p)), self.ctx,
               "pflbm_init_equilibrium")
 
+    def set_check_interval(self, every: int) -> None:
+        """Check sum(phi), sum(p*) for NaN/Inf every `every` steps (0 = off)."""
+        check(self.lib.pflbm_set_check_interval(self.ctx, int(every)), self.ctx,
+              "pflbm_set_check_interval")
+
     def step(self, n: int = 1) -> None:
         check(self.lib.pflbm_step(self.ctx, int(n)), self.ctx, "pflbm_step")
 
@@ -148,6 +153,11 @@ class Simulation:
     def load_state(self, buf: torch.Tensor, step_count: int) -> None:
         check(self.lib.pflbm_load_state(self.ctx, _ptr(buf), int(step_count)), self.ctx,
               "pflbm_load_state")
+
+    def step_states(self, src: torch.Tensor, dst: torch.Tensor, n: int) -> None:
+        """One step from saved state `src` (level n) into buffer `dst` (level n + 1)."""
+        check(self.lib.pflbm_step_states(self.ctx, _ptr(src), _ptr(dst), int(n)), self.ctx,
+              "pflbm_step_states")
 
     def profile_step(self, n: int):
         """Steps n times under HIP events; returns milliseconds

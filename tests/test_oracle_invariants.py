@@ -92,3 +92,18 @@ def test_streaming_is_a_permutation_with_bounce_back():
         a = np.sort(fstar[:, grid.fluid].reshape(-1).numpy())
         b = np.sort(out[:, grid.fluid].reshape(-1).numpy())
         assert np.array_equal(a, b)
+
+
+def test_unstable_parameters_blow_up_in_the_oracle():
+    """The case the GPU stability check is tested on is genuinely unstable:
+    tau -> 1/2 with velocities of 0.3 at density ratio 1000."""
+    p = W.Params(tau_H=0.5001, tau_L=0.5001, mobility=0.02, xi=4.0, sigma=1e-3, rho_L=1e-3)
+    wl = W.random_state(40, 24, 8, periodic=(True, True, True), params=p, u_amp=0.3, seed=77)
+    grid, prm, h, g = _setup(wl)
+    finite = True
+    for _ in range(40):
+        h, g = P.step(grid, prm, h, g)
+        if not (torch.isfinite(h).all() and torch.isfinite(g).all()):
+            finite = False
+            break
+    assert not finite
