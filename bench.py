@@ -24,17 +24,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "coupled PFLBM MLUPS & %HBM roofline; FP32 vs FP16-store; adjoint/fwd cost"
 HBM_PEAK_GBPS = 8000.0
-# algorithmic bytes per cell of the collide-and-stream kernel: read + write
-# 15 + 27 populations once, read phi once (the phi-update kernel adds the one
-# phi write of the step's 344 B (FP32) / 688 B (FP64) / 176 B (FP16 storage))
-CELL_KERNEL_BYTES = {"fp64": 42 * 8 * 2 + 8, "fp32": 42 * 4 * 2 + 4, "fp16s": 42 * 2 * 2 + 4}
+# Algorithmic bytes per cell and step (what the method must move): read and
+# write the 15 + 27 populations once each, read and write phi once.  The step
+# is one kernel (k_step), so this is also that kernel's figure.
 STEP_BYTES = {"fp64": 688, "fp32": 344, "fp16s": 176}
-# HBM bytes per launch of k_cell on the rising-bubble lattice from rocprofv3
-# FETCH_SIZE / WRITE_SIZE (mean of even and odd steps), scaled by the factors a
-# plain 2 GiB device copy gives on the same box (2.0 for FETCH_SIZE, 1.0 for
-# WRITE_SIZE); taken for the current kernels (profiles/k_cell_rising_bubble_
-# 128x512x128_hbm_traffic.txt) and to be re-measured whenever k_cell changes
-TRAFFIC = {"fp32": 3.023e9, "fp16s": 1.655e9, "fp64": 5.912e9}
+CELL_KERNEL_BYTES = STEP_BYTES
+# HBM bytes per launch of k_step on the rising-bubble lattice from rocprofv3
+# FETCH_SIZE / WRITE_SIZE, scaled by the factors a plain 2 GiB device copy
+# gives on the same box (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE); None until
+# measured for the current kernel, and to be re-measured whenever it changes
+TRAFFIC = {"fp32": None, "fp16s": None, "fp64": None}
 
 
 def log(msg):
@@ -271,7 +270,7 @@ def main():
                      "frac": round(main_form["cell_kernel_frac"], 4), "traffic": TRAFFIC.get(prec),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "algorithmic_bytes_per_launch": CELL_KERNEL_BYTES[prec] * 128 * 512 * 128,
-                     "kernel": "k_cell (fused collide-and-stream)",
+                     "kernel": "k_step (fused pull, phase field, collide, store)",
                      "bytes_per_cell": CELL_KERNEL_BYTES[prec]},
         "step_effective": {"bytes_per_cell": STEP_BYTES[prec],
                            "GBps": round(main_form["effective_GBps"], 1),

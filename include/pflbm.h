@@ -64,12 +64,21 @@ typedef enum {
   PFLBM_FP64 = 0,        /* FP64 populations, FP64 arithmetic                     */
   PFLBM_FP32 = 1,        /* FP32 populations, FP32 arithmetic                     */
   PFLBM_FP32_FP16S = 2   /* FP32 arithmetic, populations stored as FP16 of
-                            (f_i - s_i) * 2^k; for h, s_i = w_i phi of the cell
-                            that wrote the value (its phi at that step); for g,
-                            s_i = 0; k per lattice from fp16_scale_log2          */
+                            (f_i - s_i) * 2^k; for h, s_i = w_i phi^n of one
+                            cell: with PFLBM_STREAM_AB the cell that reads the
+                            value next step, with PFLBM_STREAM_AA the cell that
+                            wrote it; for g, s_i = 0; k per lattice from
+                            fp16_scale_log2                                      */
 } pflbm_precision;
 
 typedef enum { PFLBM_BGK = 0, PFLBM_MRT = 1 } pflbm_collision;
+
+/* Streaming scheme (paper: streaming eq.; both give the same results):
+ *   PFLBM_STREAM_AB: two population buffers read in pull form; one fused
+ *     kernel per step also forms phi (fastest; twice the population memory);
+ *   PFLBM_STREAM_AA: the in-place AA pattern, one population buffer; each
+ *     step is a collide-and-stream kernel plus a light phi pass. */
+typedef enum { PFLBM_STREAM_AB = 0, PFLBM_STREAM_AA = 1 } pflbm_streaming;
 
 typedef struct {
   int32_t nx, ny, nz;     /* cells per axis, each >= 1                            */
@@ -77,6 +86,7 @@ typedef struct {
   int32_t precision;      /* pflbm_precision                                      */
   int32_t collision;      /* pflbm_collision                                      */
   int32_t has_mask;       /* 1: pflbm_set_mask must be called before init          */
+  int32_t streaming;      /* pflbm_streaming                                      */
 } pflbm_desc;
 
 typedef struct {
@@ -97,8 +107,9 @@ typedef struct {
 } pflbm_params;
 
 /* Bytes of device workspace for a context with this description (256-aligned
- * regions: populations, two phi buffers, mask, reduction partials).  Returns 0
- * if the description is invalid. */
+ * regions: one (AA) or two (AB) population buffers, two phi buffers, the mask
+ * and its neighbour bits, reduction partials).  Returns 0 if the description
+ * is invalid. */
 size_t pflbm_workspace_bytes(const pflbm_desc* desc);
 
 /* Creates a host-side context that uses d_workspace (>= pflbm_workspace_bytes,
@@ -117,7 +128,8 @@ pflbm_status pflbm_destroy(pflbm_ctx* ctx);
 pflbm_status pflbm_set_params(pflbm_ctx* ctx, const pflbm_params* params);
 
 /* Copies an N-byte solid mask (1 = solid, 0 = fluid) into the workspace
- * (device-to-device, asynchronous).  Only for contexts created with has_mask. */
+ * (device-to-device, asynchronous) and derives each cell's solid-neighbour
+ * bits from it.  Only for contexts created with has_mask. */
 pflbm_status pflbm_set_mask(pflbm_ctx* ctx, const uint8_t* d_solid);
 
 /* Equilibrium initialisation: h_i = phi0 w_i [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u],
@@ -155,13 +167,14 @@ pflbm_status pflbm_read_populations(pflbm_ctx* ctx, double* d_h, double* d_g);
  * Waits for the stream.  Returns PFLBM_ERR_UNSTABLE if any is NaN/Inf. */
 pflbm_status pflbm_reduce(pflbm_ctx* ctx, double out_host[5]);
 
-/* Bytes of one saved state (populations in storage precision, then the
- * current and the previous phi field). */
+/* Bytes of one saved state: h [15][N] and g [27][N] in storage precision
+ * (layout of the streaming scheme), phi^n [N] and, for FP16S storage only,
+ * phi^{n-1} [N] (the shift reference; defined on fluid cells). */
 size_t pflbm_state_bytes(const pflbm_ctx* ctx);
 
 /* Copies the state to / from d_buf (device-to-device, asynchronous).  The
- * step count is not part of the buffer: load takes it explicitly (its parity
- * selects the in-place streaming layout). */
+ * step count is not part of the buffer: load takes it explicitly (with
+ * PFLBM_STREAM_AA its parity selects the layout). */
 pflbm_status pflbm_save_state(pflbm_ctx* ctx, void* d_dst);
 pflbm_status pflbm_load_state(pflbm_ctx* ctx, const void* d_src, int64_t step_count);
 
@@ -177,8 +190,9 @@ int64_t pflbm_step_count(const pflbm_ctx* ctx);
 /* Advances nsteps like pflbm_step while timing every kernel with HIP events
  * recorded on the context's stream between consecutive launches (no host
  * synchronisation inside the loop); out_ms_host receives {summed durations of
- * the collide-and-stream kernel, summed durations of the phi-update kernel,
- * total elapsed time} in milliseconds.  Waits for the stream at the end. */
+ * the collide-and-stream kernel, summed durations of the phi-update kernel
+ * (0 with PFLBM_STREAM_AB, whose step kernel forms phi itself), total elapsed
+ * time} in milliseconds.  Waits for the stream at the end. */
 pflbm_status pflbm_profile_step(pflbm_ctx* ctx, int64_t nsteps, double out_ms_host[3]);
 
 /* Waits for all work on the context's stream. */

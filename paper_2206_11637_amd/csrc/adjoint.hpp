@@ -337,12 +337,12 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
 template <typename S>
 struct AdjArgs {
   using R = typename Store<S>::R;
-  // primal state of level n (a saved state: populations in the AA layout of
-  // step n's parity, then the phi field)
+  // primal state of level n (a saved state: populations in the layout of the
+  // streaming scheme, then phi^n and, for FP16 storage, phi^{n-1})
   const S* ph;
   const S* pg;
   const R* pphi;
-  const R* pphi_prev;   // phi^{n-1}: writers of the level-n populations (FP16 shifts)
+  const R* pphi_prev;   // phi^{n-1}: FP16 shift reference of the level-n populations
   const unsigned char* mask;
   // adjoint of level n+1 (natural layout) and of level n
   const R* lh_in;
@@ -358,19 +358,18 @@ struct AdjArgs {
   Codec<R> cd;
 };
 
-template <typename S, bool MRT, bool ODD, bool MASK>
+template <typename S, bool MRT, int RULE, bool MASK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<S>::value)))
 void k_adj_cell(AdjArgs<S> a) {
-  using R = typename Store<S>::R;
+  using St = Store<S>;
+  using R = typename St::R;
   extern __shared__ unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   __shared__ double red[4][2];
   const Geom& G = a.geo;
   const int TX = G.bx + 2, TY = G.by + 2;
-  R* tile_prev = tile + TX * TY * 3;
   const TileCoord t = tile_of_block(G);
   load_phi_tile<R, MASK>(tile, a.pphi, a.mask, G, t);
-  if (Store<S>::kShift) load_phi_tile<R, MASK>(tile_prev, a.pphi_prev, a.mask, G, t);
   __syncthreads();
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
@@ -379,10 +378,9 @@ void k_adj_cell(AdjArgs<S> a) {
     const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
     const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
     const Nbhd nb = make_nbhd(x, y, z, G);
-    R phw[Q_H];
-    if (Store<S>::kShift) writer_phi_tile(tile_prev, TX, TY, lx, ly, walls, phw);
-    R h[Q_H], g[Q_G];
-    load_pops<S, ODD>(a.ph, a.pg, G.N, idx, nb, walls, a.cd, phw, h, g);
+    R ref[Q_H], h[Q_H], g[Q_G];
+    shift_refs<S, RULE>(a.pphi_prev, idx, nb, walls, ref);
+    load_pops<S, RULE, false>(a.ph, a.pg, G.N, idx, nb, walls, a.cd, ref, h, g);
     R Gx, Gy, Gz, lap;
     stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
     // transposed streaming: Lambda of the slot each post-collision value went to

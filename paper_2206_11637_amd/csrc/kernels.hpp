@@ -1,31 +1,48 @@
 // Forward kernels of the coupled phase-field LBM step on gfx950.
 //
 // Data layout in HBM (all structure-of-arrays, x fastest):
-//   h[i * N + idx], i < 15       phase-field populations (storage type S)
-//   g[i * N + idx], i < 27       hydrodynamic populations
-//   phi[2][N]                    phase field, double-buffered (compute type R):
-//                                phi^n (stencil source) and phi^{n-1}
-//   mask[N]                      optional solids (1 = solid)
+//   h[i * N + idx], i < 15       phase-field populations (storage type S),
+//   g[i * N + idx], i < 27       hydrodynamic populations; two state buffers
+//                                of each (the step reads one, writes the other)
+//   phi[2][N]                    phase field (compute type R)
+//   mask[N], nbr[N]              optional solids (1 = solid) and, per cell, the
+//                                bit set of its solid neighbours (bit 0: the
+//                                cell itself is solid)
 //
-// Streaming is the in-place AA pattern (one population buffer per lattice):
+// Streaming (paper: streaming eq., bounce-back walls) comes in two schemes.
+//
+// Two buffers, pull form (the default, fastest).  Slot (i, x) of a state
+// buffer holds the post-collision value f*_i(x) of the step that wrote it
+// (the initialisation writes the equivalent values).  The pre-collision
+// population i of cell y is
+//     slot(i, y - c_i)   if y - c_i is fluid,
+//     slot(opp i, y)     otherwise (halfway bounce-back),
+// so every fluid slot is read exactly once per step, and a step writes only
+// its own cells' slots of the other buffer (aligned, coalesced stores).
+// The fused step kernel k_step gives each block a bx * by tile and a chunk of
+// z planes and marches up the chunk.  The phase field phi^n = sum_i h_i is
+// never read from HBM: for each plane the block pulls the h populations of
+// its cells and of a one-cell ring around the tile, sums them into a 4-plane
+// LDS ring (sentinel for walls and solids), and keeps its own cells' pulled
+// h in registers for the collision one plane later.  The grad/lap stencils
+// read three ring planes.  Pulling the ring cells' h re-reads data that the
+// neighbouring tiles read too (mostly from L2).  This needs the second
+// buffer: in place, a neighbouring block could overwrite a ring cell's
+// populations before they are summed.
+//
+// In-place AA pattern (one buffer per lattice, half the population memory):
 //   even step: read own slots f[i][x], write f*_i into own slot f[opp i][x];
 //   odd step:  read f_i(x) from f[opp i][x - c_i] (or f[i][x] when x - c_i is
 //              a wall/solid: the value bounced back there), write f*_i into
 //              f[i][x + c_i] (or f[opp i][x] when x + c_i is a wall/solid).
-// Every slot is read and written by exactly one cell per step, which makes
-// the update race-free without a second population buffer; halfway
-// bounce-back falls out of the redirected addresses (paper: streaming
-// eq. and bounce-back walls).  After an odd step the buffer holds the
-// natural layout f[i][x] = f_i(x).
-//
-// One thread per cell.  A block is a bx * by tile of one z plane (256
-// threads); it stages phi of the tile plus a one-cell halo on three planes in
-// LDS, where out-of-box and solid neighbours carry a sentinel.  The sentinel
-// both selects the wall rule of the phi stencils and tells the AA addressing
-// which neighbours are walls, so no mask read is needed on the hot path.
+// Every slot is read and written by exactly one cell per step, so the update
+// is race-free in place; after an odd step the buffer holds the natural
+// layout f[i][x] = f_i(x).  k_cell_aa does one plane of one tile per block
+// with phi^n staged from the stored field (tile + halo, 3 planes, in LDS),
+// and a light pass (k_light, gather) then forms phi^{n+1}.
 //
 // Blocks are issued round-robin over the 8 XCDs; xcd_remap() renumbers them
-// so that each XCD walks one contiguous slab of tiles, keeping the halo and
+// so that each XCD walks one contiguous range of tiles, keeping the ring and
 // neighbour-population reuse inside one XCD's L2.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -40,16 +57,20 @@ struct Geom {
   int px, py, pz;         // periodic flags
   int bx, by;             // tile shape (bx * by == 256)
   int tiles_x, tiles_y;
-  unsigned nblocks;       // tiles_x * tiles_y * nz
+  unsigned nblocks;       // tiles_x * tiles_y * nz (one plane per block)
+  int zc, nchunks;        // z-chunk length and count of the marching step kernel
+  unsigned nblocks_step;  // tiles_x * tiles_y * nchunks
   long long N;
 };
 
 // ---- storage codecs -------------------------------------------------------
 // ld/st take the shift s and the scale: stored = (f - s) * 2^k.  FP64 and
-// FP32 store f itself.  FP16 storage shifts every h population by w_i times
-// the phase field of the cell that wrote it (phi^n of the writer, which the
-// reader finds in the previous phi buffer), so both pure phases store values
-// near zero; g is stored unshifted (it is small in the p* gauge).
+// FP32 store f itself.  FP16 storage shifts every h population by w_i times a
+// phase field one step old, so both pure phases store values near zero; g is
+// stored unshifted (it is small in the p* gauge).  Two buffers: the phase
+// field phi^n of the cell that will read the value in step n + 1 (the reader
+// finds it at its own index of the previous phi buffer).  AA: phi^n of the
+// cell that wrote it (x - c_i, or x itself behind a wall, in both parities).
 template <typename S>
 struct Store;
 template <bool NT, typename T>
@@ -92,18 +113,18 @@ struct Store<_Float16> {
   }
 };
 
-// Cache policy of the population streams (measured on the rising-bubble
-// lattice, FP32, per step: 0.849 ms all-streaming -> 0.721 ms with this one):
-//   even steps (own slots, aligned rows): non-temporal loads and stores;
-//   odd steps (neighbour slots, rows one element off alignment, lines shared
-//     by neighbouring waves): cached loads, non-temporal stores;
-//   phi update: cached loads (the next collide-and-stream re-reads h, part of
-//     which the 256 MB last-level cache then still holds).
-template <bool ODD> struct PopPolicy {
-  static constexpr bool nt_load = !ODD;
-  static constexpr bool nt_store = true;
-};
-constexpr bool kNtGather = false;
+// Cache policy of the population streams: pulls read rows one element off
+// alignment whose lines neighbouring waves and the ring share (cached loads);
+// the step's stores are written once and read only in the next step
+// (non-temporal).
+#ifndef PFLBM_NT_PULL
+#define PFLBM_NT_PULL 0
+#endif
+#ifndef PFLBM_NT_STORE
+#define PFLBM_NT_STORE 1
+#endif
+constexpr bool kNtPull = PFLBM_NT_PULL;
+constexpr bool kNtStore = PFLBM_NT_STORE;
 
 template <typename R>
 struct Codec {
@@ -128,11 +149,65 @@ __device__ __forceinline__ TileCoord tile_of_block(const Geom& G) {
   return TileCoord{int(tx) * G.bx, int(ty) * G.by, int(rest / G.tiles_y)};
 }
 
-// Neighbour coordinates with periodic wrap; returns false outside a wall.
+struct ChunkCoord { int x0, y0, z0, z1; };
+
+__device__ __forceinline__ ChunkCoord chunk_of_block(const Geom& G) {
+  const unsigned L = xcd_remap(blockIdx.x, G.nblocks_step);
+  const unsigned tx = L % G.tiles_x;
+  const unsigned rest = L / G.tiles_x;
+  const unsigned ty = rest % G.tiles_y;
+  const int z0 = int(rest / G.tiles_y) * G.zc;
+  return ChunkCoord{int(tx) * G.bx, int(ty) * G.by, z0, min(z0 + G.zc, G.nz)};
+}
+
+// Coordinate one step outside [0, n): wrapped on a periodic axis, else a
+// wall (false).  Positions further out (a ragged tile's padding) are never a
+// neighbour of a cell and report false as well.
 __device__ __forceinline__ bool wrap(int& v, int n, int periodic) {
-  if (v < 0) { if (!periodic) return false; v += n; }
-  else if (v >= n) { if (!periodic) return false; v -= n; }
+  if (v == -1) { if (!periodic) return false; v = n - 1; }
+  else if (v == n) { if (!periodic) return false; v = 0; }
+  else if (v < -1 || v > n) return false;
   return true;
+}
+
+// ---- wall bits -------------------------------------------------------------
+// Bit k set: the neighbour in direction kC27[k] is outside a wall or solid.
+struct AxisMasks { unsigned xm, xp, ym, yp, zm, zp; };
+constexpr AxisMasks make_axis_masks() {
+  AxisMasks m{0u, 0u, 0u, 0u, 0u, 0u};
+  for (int k = 1; k < 27; ++k) {
+    if (kC27[k].x < 0) m.xm |= 1u << k;
+    if (kC27[k].x > 0) m.xp |= 1u << k;
+    if (kC27[k].y < 0) m.ym |= 1u << k;
+    if (kC27[k].y > 0) m.yp |= 1u << k;
+    if (kC27[k].z < 0) m.zm |= 1u << k;
+    if (kC27[k].z > 0) m.zp |= 1u << k;
+  }
+  return m;
+}
+constexpr AxisMasks kAxis = make_axis_masks();
+
+// the box faces that are walls, from the coordinates alone
+__device__ __forceinline__ unsigned box_walls(int x, int y, int z, const Geom& G) {
+  unsigned b = 0;
+  if (!G.px) { b |= (x == 0) ? kAxis.xm : 0u; b |= (x == G.nx - 1) ? kAxis.xp : 0u; }
+  if (!G.py) { b |= (y == 0) ? kAxis.ym : 0u; b |= (y == G.ny - 1) ? kAxis.yp : 0u; }
+  if (!G.pz) { b |= (z == 0) ? kAxis.zm : 0u; b |= (z == G.nz - 1) ? kAxis.zp : 0u; }
+  return b;
+}
+
+// Box walls plus solid neighbours; `solid` reports the cell itself.
+template <bool MASK>
+__device__ __forceinline__ unsigned cell_walls(int x, int y, int z, unsigned idx, const Geom& G,
+                                               const unsigned* __restrict__ nbr, bool& solid) {
+  unsigned b = box_walls(x, y, z, G);
+  solid = false;
+  if (MASK) {
+    const unsigned m = nbr[idx];
+    solid = m & 1u;
+    b |= m & ~1u;
+  }
+  return b;
 }
 
 // Stage phi of the tile + halo (3 planes) into LDS; sentinel for walls/solids.
@@ -155,7 +230,7 @@ __device__ __forceinline__ void load_phi_tile(R* tile, const R* __restrict__ phi
 }
 
 // Linear indices of the 3x3x3 neighbourhood (periodic wrap; out-of-box
-// entries are never dereferenced because the tile marks them as walls).
+// entries are never dereferenced because the wall bits mark them).
 // 32-bit: the library limits N * sizeof(storage) below 2^32.
 struct Nbhd {
   unsigned xs[3], ys[3], zs[3];
@@ -193,7 +268,7 @@ __device__ __forceinline__ const S* slot(const S* base, long long N, int pop, un
   return reinterpret_cast<const S*>(b + (unsigned)(cell * (unsigned)sizeof(S)));
 }
 
-// Bit k of the result: neighbour in direction kC27[k] is a wall or solid.
+// Wall bits of a cell from an LDS tile of 3 planes (sentinel = wall/solid).
 template <typename R>
 __device__ __forceinline__ unsigned wall_bits(const R* tile, int TX, int TY, int lx, int ly) {
   unsigned b = 0;
@@ -206,21 +281,23 @@ __device__ __forceinline__ unsigned wall_bits(const R* tile, int TX, int TY, int
   return b;
 }
 
-// grad phi and lap phi from the LDS tile (missing neighbours repeat phi(x)),
-// over opposite pairs: the gradient takes each pair's difference, the
-// Laplacian its sum.
+// grad phi and lap phi from three LDS planes (below, own, above; missing
+// neighbours repeat phi(x)), over opposite pairs: the gradient takes each
+// pair's difference, the Laplacian its sum.
 template <typename R>
-__device__ __forceinline__ void stencil(const R* tile, int TX, int TY, int lx, int ly, R& Gx,
-                                        R& Gy, R& Gz, R& lap) {
-  const R p0 = tile[(TY + ly + 1) * TX + lx + 1];
+__device__ __forceinline__ void stencil3(const R* pm, const R* p0, const R* pp, int TX, int lx,
+                                         int ly, R& Gx, R& Gy, R& Gz, R& lap) {
+  const R c0 = p0[(ly + 1) * TX + lx + 1];
   Gx = Gy = Gz = lap = R(0);
 #pragma unroll
   for (int k = 1; k < 27; k += 2) {
     const Dir d = cg(k);
-    const R va = tile[((1 + d.z) * TY + (ly + 1 + d.y)) * TX + (lx + 1 + d.x)];
-    const R vb = tile[((1 - d.z) * TY + (ly + 1 - d.y)) * TX + (lx + 1 - d.x)];
-    const R da = (va == sentinel<R>()) ? R(0) : va - p0;
-    const R db = (vb == sentinel<R>()) ? R(0) : vb - p0;
+    const R* pa = d.z < 0 ? pm : (d.z > 0 ? pp : p0);
+    const R* pb = d.z < 0 ? pp : (d.z > 0 ? pm : p0);
+    const R va = pa[(ly + 1 + d.y) * TX + (lx + 1 + d.x)];
+    const R vb = pb[(ly + 1 - d.y) * TX + (lx + 1 - d.x)];
+    const R da = (va == sentinel<R>()) ? R(0) : va - c0;
+    const R db = (vb == sentinel<R>()) ? R(0) : vb - c0;
     const R w = R(wg(k));
     const R odd = w * (da - db);
     if (d.x) Gx += d.x > 0 ? odd : -odd;
@@ -234,15 +311,18 @@ __device__ __forceinline__ void stencil(const R* tile, int TX, int TY, int lx, i
   lap *= R(6);
 }
 
-// ---- population access (AA pattern) --------------------------------------
-// Population i arriving at cell x was written by x - c_i, or by x itself when
-// x - c_i is a wall or solid (bounce-back); this holds for both parities.
-// phw[i] is the phase field of that writer (only used by FP16 storage).
-//
-// Addresses: an opposite pair (i, i+1), i odd, is addressed from the pair's
-// first population (a wave-uniform base); the per-lane part is one 32-bit byte
+// the same from a contiguous 3-plane tile
+template <typename R>
+__device__ __forceinline__ void stencil(const R* tile, int TX, int TY, int lx, int ly, R& Gx,
+                                        R& Gy, R& Gz, R& lap) {
+  stencil3(tile, tile + TX * TY, tile + 2 * TX * TY, TX, lx, ly, Gx, Gy, Gz, lap);
+}
+
+// ---- population access (pull form) -----------------------------------------
+// An opposite pair (i, i+1), i odd, is addressed from the pair's first
+// population (a wave-uniform base); the per-lane part is one 32-bit byte
 // offset, cell * sizeof(S) plus N * sizeof(S) for the pair's second member.
-// In odd steps the lane picks between the neighbour slot and its own
+// The pull picks between the neighbour's slot and the cell's own
 // (bounce-back) slot with a single select on that offset.
 __device__ __forceinline__ constexpr int pair_first(int i) { return i == 0 ? 0 : ((i & 1) ? i : i - 1); }
 __device__ __forceinline__ constexpr bool pair_second(int i) { return i != 0 && !(i & 1); }
@@ -263,11 +343,90 @@ __device__ __forceinline__ unsigned pair_off(int i, unsigned cell, unsigned NS) 
   return cell * (unsigned)sizeof(S) + (pair_second(i) ? NS : 0u);
 }
 
-template <typename S, bool ODD>
+// offset of the slot that population i of cell idx is pulled from
+template <typename S, bool G27>
+__device__ __forceinline__ unsigned pull_off(int i, unsigned idx, const Nbhd& nb, unsigned walls,
+                                             unsigned NS) {
+  if (i == 0) return pair_off<S>(0, idx, NS);
+  const Dir d = cdir<G27>(i);
+  return (walls & (1u << nb27(-d.x, -d.y, -d.z))) ? pair_off<S>(opp(i), idx, NS)
+                                                   : pair_off<S>(i, nb.at(-d.x, -d.y, -d.z), NS);
+}
+
+// Pre-collision h of one cell.  phi_prev: the cell's own phase field one step
+// earlier (the FP16 shift reference).
+template <typename S, bool NT>
+__device__ __forceinline__ void pull_h(const S* __restrict__ H, long long N, unsigned idx,
+                                       const Nbhd& nb, unsigned walls,
+                                       typename Store<S>::R phi_prev,
+                                       typename Store<S>::R inv_scale,
+                                       typename Store<S>::R (&h)[Q_H]) {
+  using St = Store<S>;
+  using R = typename St::R;
+  const unsigned NS = (unsigned)(N * (long long)sizeof(S));
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    const S* p = reinterpret_cast<const S*>(pair_base(H, N, i) + pull_off<S, false>(i, idx, nb, walls, NS));
+    h[i] = St::template ld<NT>(p, St::kShift ? R(wh(i)) * phi_prev : R(0), inv_scale);
+  }
+}
+
+template <typename S, bool NT>
+__device__ __forceinline__ void pull_g(const S* __restrict__ Gp, long long N, unsigned idx,
+                                       const Nbhd& nb, unsigned walls,
+                                       typename Store<S>::R inv_scale,
+                                       typename Store<S>::R (&g)[Q_G]) {
+  using St = Store<S>;
+  using R = typename St::R;
+  const unsigned NS = (unsigned)(N * (long long)sizeof(S));
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    const S* p = reinterpret_cast<const S*>(pair_base(Gp, N, i) + pull_off<S, true>(i, idx, nb, walls, NS));
+    g[i] = St::template ld<NT>(p, R(0), inv_scale);
+  }
+}
+
+// Post-collision values into the cell's own slots.  phr[i]: the phase field
+// phi^n of the cell that pulls slot (i, x) next step (x + c_i, or x itself
+// behind a wall); only FP16 storage uses it.
+template <typename S, bool NT>
+__device__ __forceinline__ void store_own(S* __restrict__ H, S* __restrict__ Gp, long long N,
+                                          unsigned idx, const Codec<typename Store<S>::R>& cd,
+                                          const typename Store<S>::R (&phr)[Q_H],
+                                          const typename Store<S>::R (&h)[Q_H],
+                                          const typename Store<S>::R (&g)[Q_G]) {
+  using St = Store<S>;
+  using R = typename St::R;
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i)
+    St::template st<NT>(slot(H, N, i, idx), h[i], St::kShift ? R(wh(i)) * phr[i] : R(0), cd.scale_h);
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) St::template st<NT>(slot(Gp, N, i, idx), g[i], R(0), cd.scale_g);
+}
+
+// ---- read rules of a state ---------------------------------------------------
+// RULE_AB: two-buffer pull; RULE_AA_EVEN / RULE_AA_ODD: the AA parity of the
+// next step (a state after n steps is read with the rule of parity n).
+enum Rule { RULE_AB = 0, RULE_AA_EVEN = 1, RULE_AA_ODD = 2 };
+
+// offset of the slot population i of cell idx is read from (pair base relative)
+template <typename S, bool G27, int RULE>
+__device__ __forceinline__ unsigned read_off(int i, unsigned idx, const Nbhd& nb, unsigned walls,
+                                             unsigned NS) {
+  if (RULE == RULE_AB) return pull_off<S, G27>(i, idx, nb, walls, NS);
+  if (RULE == RULE_AA_EVEN || i == 0) return pair_off<S>(i, idx, NS);
+  const Dir d = cdir<G27>(i);
+  return (walls & (1u << nb27(-d.x, -d.y, -d.z))) ? pair_off<S>(i, idx, NS)
+                                                   : pair_off<S>(opp(i), nb.at(-d.x, -d.y, -d.z), NS);
+}
+
+// Pre-collision populations of one cell under a read rule.  ref[i]: the FP16
+// shift reference of population i (only used by FP16 storage).
+template <typename S, int RULE, bool NT>
 __device__ __forceinline__ void load_pops(const S* __restrict__ H, const S* __restrict__ Gp,
                                           long long N, unsigned idx, const Nbhd& nb,
                                           unsigned walls, const Codec<typename Store<S>::R>& cd,
-                                          const typename Store<S>::R (&phw)[Q_H],
+                                          const typename Store<S>::R (&ref)[Q_H],
                                           typename Store<S>::R (&h)[Q_H],
                                           typename Store<S>::R (&g)[Q_G]) {
   using St = Store<S>;
@@ -275,35 +434,79 @@ __device__ __forceinline__ void load_pops(const S* __restrict__ H, const S* __re
   const unsigned NS = (unsigned)(N * (long long)sizeof(S));
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
-    unsigned off = pair_off<S>(i, idx, NS);
-    if (ODD && i) {
-      const Dir d = ch(i);
-      if (!(walls & (1u << nb27(-d.x, -d.y, -d.z)))) off = pair_off<S>(opp(i), nb.at(-d.x, -d.y, -d.z), NS);
-    }
-    const S* p = reinterpret_cast<const S*>(pair_base(H, N, i) + off);
-    h[i] = St::template ld<PopPolicy<ODD>::nt_load>(p, St::kShift ? R(wh(i)) * phw[i] : R(0), cd.inv_scale_h);
+    const S* p = reinterpret_cast<const S*>(pair_base(H, N, i) + read_off<S, false, RULE>(i, idx, nb, walls, NS));
+    h[i] = St::template ld<NT>(p, St::kShift ? R(wh(i)) * ref[i] : R(0), cd.inv_scale_h);
   }
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) {
-    unsigned off = pair_off<S>(i, idx, NS);
-    if (ODD && i) {
-      const Dir d = cg(i);
-      if (!(walls & (1u << nb27(-d.x, -d.y, -d.z)))) off = pair_off<S>(opp(i), nb.at(-d.x, -d.y, -d.z), NS);
-    }
-    const S* p = reinterpret_cast<const S*>(pair_base(Gp, N, i) + off);
-    g[i] = St::template ld<PopPolicy<ODD>::nt_load>(p, R(0), cd.inv_scale_g);
+    const S* p = reinterpret_cast<const S*>(pair_base(Gp, N, i) + read_off<S, true, RULE>(i, idx, nb, walls, NS));
+    g[i] = St::template ld<NT>(p, R(0), cd.inv_scale_g);
   }
 }
 
-// phi_self: the writer's own phi^n (the field value, bit-identical to what
-// the readers of the next step look up).
-template <typename S, bool ODD>
-__device__ __forceinline__ void store_pops(S* __restrict__ H, S* __restrict__ Gp, long long N,
+template <typename S, int RULE, bool NT>
+__device__ __forceinline__ void load_h(const S* __restrict__ H, long long N, unsigned idx,
+                                       const Nbhd& nb, unsigned walls,
+                                       const Codec<typename Store<S>::R>& cd,
+                                       const typename Store<S>::R (&ref)[Q_H],
+                                       typename Store<S>::R (&h)[Q_H]) {
+  using St = Store<S>;
+  using R = typename St::R;
+  const unsigned NS = (unsigned)(N * (long long)sizeof(S));
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    const S* p = reinterpret_cast<const S*>(pair_base(H, N, i) + read_off<S, false, RULE>(i, idx, nb, walls, NS));
+    h[i] = St::template ld<NT>(p, St::kShift ? R(wh(i)) * ref[i] : R(0), cd.inv_scale_h);
+  }
+}
+
+// FP16 shift references of the populations a cell reads, from a phi^{n-1}
+// buffer: two buffers, the cell's own value; AA, the writer's (x - c_i, or x
+// behind a wall).  Zero when unused.
+template <typename S, int RULE>
+__device__ __forceinline__ void shift_refs(const typename Store<S>::R* __restrict__ phi_prev,
                                            unsigned idx, const Nbhd& nb, unsigned walls,
-                                           const Codec<typename Store<S>::R>& cd,
-                                           typename Store<S>::R phi_self,
-                                           const typename Store<S>::R (&h)[Q_H],
-                                           const typename Store<S>::R (&g)[Q_G]) {
+                                           typename Store<S>::R (&ref)[Q_H]) {
+  using R = typename Store<S>::R;
+  if (!Store<S>::kShift) {
+#pragma unroll
+    for (int i = 0; i < Q_H; ++i) ref[i] = R(0);
+    return;
+  }
+  const R self = phi_prev[idx];
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    if (RULE == RULE_AB || i == 0) {
+      ref[i] = self;
+    } else {
+      const Dir d = ch(i);
+      ref[i] = (walls & (1u << nb27(-d.x, -d.y, -d.z))) ? self : phi_prev[nb.at(-d.x, -d.y, -d.z)];
+    }
+  }
+}
+
+// AA writer references from an LDS tile (3 planes + halo) of phi^{n-1}
+template <typename R>
+__device__ __forceinline__ void writer_refs_tile(const R* tp, int TX, int TY, int lx, int ly,
+                                                 unsigned walls, R (&ref)[Q_H]) {
+  const R self = tp[(TY + ly + 1) * TX + lx + 1];
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i) {
+    const Dir d = ch(i);
+    ref[i] = (i == 0 || (walls & (1u << nb27(-d.x, -d.y, -d.z))))
+                 ? self
+                 : tp[((1 - d.z) * TY + (ly + 1 - d.y)) * TX + (lx + 1 - d.x)];
+  }
+}
+
+// AA store of post-collision values; phi_self: the writer's phi^n (FP16 shift)
+template <typename S, bool ODD, bool NT>
+__device__ __forceinline__ void store_aa(S* __restrict__ H, S* __restrict__ Gp, long long N,
+                                         unsigned idx, const Nbhd& nb, unsigned walls,
+                                         const Codec<typename Store<S>::R>& cd,
+                                         typename Store<S>::R phi_self,
+                                         const typename Store<S>::R (&h)[Q_H],
+                                         const typename Store<S>::R (&g)[Q_G]) {
   using St = Store<S>;
   using R = typename St::R;
   const unsigned NS = (unsigned)(N * (long long)sizeof(S));
@@ -315,7 +518,7 @@ __device__ __forceinline__ void store_pops(S* __restrict__ H, S* __restrict__ Gp
       if (!(walls & (1u << nb27(d.x, d.y, d.z)))) off = pair_off<S>(i, nb.at(d.x, d.y, d.z), NS);
     }
     S* p = reinterpret_cast<S*>(pair_base(H, N, i) + off);
-    St::template st<PopPolicy<ODD>::nt_store>(p, h[i], St::kShift ? R(wh(i)) * phi_self : R(0), cd.scale_h);
+    St::template st<NT>(p, h[i], St::kShift ? R(wh(i)) * phi_self : R(0), cd.scale_h);
   }
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) {
@@ -325,68 +528,185 @@ __device__ __forceinline__ void store_pops(S* __restrict__ H, S* __restrict__ Gp
       if (!(walls & (1u << nb27(d.x, d.y, d.z)))) off = pair_off<S>(i, nb.at(d.x, d.y, d.z), NS);
     }
     S* p = reinterpret_cast<S*>(pair_base(Gp, N, i) + off);
-    St::template st<PopPolicy<ODD>::nt_store>(p, g[i], R(0), cd.scale_g);
+    St::template st<NT>(p, g[i], R(0), cd.scale_g);
   }
 }
 
-// Writer phase fields from an LDS tile (3 planes + halo) of phi^{n-1}.
-template <typename R>
-__device__ __forceinline__ void writer_phi_tile(const R* tp, int TX, int TY, int lx, int ly,
-                                                unsigned walls, R (&phw)[Q_H]) {
-  const R self = tp[(TY + ly + 1) * TX + lx + 1];
-#pragma unroll
-  for (int i = 0; i < Q_H; ++i) {
-    const Dir d = ch(i);
-    phw[i] = (walls & (1u << nb27(-d.x, -d.y, -d.z)))
-                 ? self
-                 : tp[((1 - d.z) * TY + (ly + 1 - d.y)) * TX + (lx + 1 - d.x)];
-  }
-}
+// Occupancy request of the step kernels: 3 waves per SIMD (<= 168 VGPRs)
+// for the FP32-arithmetic forms; the FP64 form keeps the compiler's choice.
+#ifndef PFLBM_F64_WAVES
+#define PFLBM_F64_WAVES 1
+#endif
+template <typename S>
+struct StepWaves { static constexpr int value = sizeof(S) == 8 ? PFLBM_F64_WAVES : 3; };
 
-// Writer phase fields read directly from a phi buffer.
-template <typename R>
-__device__ __forceinline__ void writer_phi_direct(const R* __restrict__ phi, unsigned idx,
-                                                  const Nbhd& nb, unsigned walls, R (&phw)[Q_H]) {
-  const R self = phi[idx];
+template <typename S>
+struct StepArgs {
+  using R = typename Store<S>::R;
+  const S* h_in;             // state n
+  const S* g_in;
+  S* h_out;                  // state n + 1
+  S* g_out;
+  const R* phi_prev;         // phi^{n-1} (FP16 storage: shift reference of state n)
+  R* phi_out;                // phi^n, written for FP16 storage (null otherwise)
+  const unsigned* nbr;       // solid-neighbour bits (mask only)
+  Geom geo;
+  Phys<R> P;
+  Codec<R> cd;
+};
+
+// Fused step n -> n+1: pull, phi^n and its stencils, collide both lattices,
+// store.  One barrier per plane; the 4-plane ring lets plane z+1 be written
+// while plane z-1 is still being read.
+template <typename S, bool MRT, bool MASK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<S>::value)))
+void k_step(StepArgs<S> a) {
+  using St = Store<S>;
+  using R = typename St::R;
+  extern __shared__ unsigned char smem_raw[];
+  R* ring = reinterpret_cast<R*>(smem_raw);     // [4][TY][TX]
+  const Geom& G = a.geo;
+  const int TX = G.bx + 2, TY = G.by + 2, TXY = TX * TY;
+  const ChunkCoord t = chunk_of_block(G);
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + ly * G.bx;
+  const int x = t.x0 + lx, y = t.y0 + ly;
+  const bool active = x < G.nx && y < G.ny;
+  // the cell whose phi fills this thread's own ring position (x, y wrapped
+  // for a ragged tile's first padding column/row on a periodic axis)
+  int ox = x, oy = y;
+  const bool own_ok = wrap(ox, G.nx, G.px) && wrap(oy, G.ny, G.py);
+  const int opos = (ly + 1) * TX + lx + 1;
+  // ring cell handled by this thread: rows below/above the tile, then the
+  // columns left/right of it
+  const int NH = 2 * TX + 2 * G.by;
+  int hpos = 0, hx = 0, hy = 0;
+  bool halo_ok = false;
+  if (tid < NH) {
+    int ix, iy;
+    if (tid < TX) { ix = tid; iy = 0; }
+    else if (tid < 2 * TX) { ix = tid - TX; iy = TY - 1; }
+    else if (tid < 2 * TX + G.by) { ix = 0; iy = 1 + tid - 2 * TX; }
+    else { ix = TX - 1; iy = 1 + tid - 2 * TX - G.by; }
+    hpos = iy * TX + ix;
+    hx = t.x0 - 1 + ix;
+    hy = t.y0 - 1 + iy;
+    halo_ok = wrap(hx, G.nx, G.px) && wrap(hy, G.ny, G.py);
+  }
+  const unsigned sxy = (unsigned)G.nx * (unsigned)G.ny;
+
+  // phi^n of plane p (own position kept: pulled h, walls, solid flag)
+  R hn[Q_H];
+  unsigned wn = 0;
+  bool sn = true;
+  auto plane = [&](int p) {
+    int pz = p;
+    const bool zok = wrap(pz, G.nz, G.pz);
+    R* rp = ring + (p & 3) * TXY;
+    R v = sentinel<R>();
+    sn = true;
+    if (own_ok && zok) {
+      const unsigned idx = ox + G.nx * oy + sxy * pz;
+      bool sol;
+      wn = cell_walls<MASK>(ox, oy, pz, idx, G, a.nbr, sol);
+      if (!sol) {
+        const R pp = St::kShift ? a.phi_prev[idx] : R(0);
+        pull_h<S, kNtPull>(a.h_in, G.N, idx, make_nbhd(ox, oy, pz, G), wn, pp, a.cd.inv_scale_h, hn);
+        v = sum_h(hn);
+        sn = false;
+      }
+    }
+    rp[opos] = v;
+    if (tid < NH) {
+      R hv = sentinel<R>();
+      if (halo_ok && zok) {
+        const unsigned idx = hx + G.nx * hy + sxy * pz;
+        bool sol;
+        const unsigned w = cell_walls<MASK>(hx, hy, pz, idx, G, a.nbr, sol);
+        if (!sol) {
+          const R pp = St::kShift ? a.phi_prev[idx] : R(0);
+          R hh[Q_H];
+          pull_h<S, false>(a.h_in, G.N, idx, make_nbhd(hx, hy, pz, G), w, pp, a.cd.inv_scale_h, hh);
+          hv = sum_h(hh);
+        }
+      }
+      rp[hpos] = hv;
+    }
+  };
+
+  plane(t.z0 - 1);
+  plane(t.z0);
+  for (int z = t.z0; z < t.z1; ++z) {
+    R h[Q_H];
 #pragma unroll
-  for (int i = 0; i < Q_H; ++i) {
-    const Dir d = ch(i);
-    phw[i] = (walls & (1u << nb27(-d.x, -d.y, -d.z))) ? self : phi[nb.at(-d.x, -d.y, -d.z)];
+    for (int i = 0; i < Q_H; ++i) h[i] = hn[i];
+    const unsigned walls = wn;
+    const bool work = active && !sn;
+    const unsigned idx = x + G.nx * y + sxy * z;
+    const Nbhd nb = make_nbhd(x, y, z, G);
+    R g[Q_G];
+    if (work) pull_g<S, kNtPull>(a.g_in, G.N, idx, nb, walls, a.cd.inv_scale_g, g);
+    plane(z + 1);
+    __syncthreads();
+    if (work) {
+      const R* pm = ring + ((z - 1) & 3) * TXY;
+      const R* p0 = ring + (z & 3) * TXY;
+      const R* pp = ring + ((z + 1) & 3) * TXY;
+      R Gx, Gy, Gz, lap;
+      stencil3(pm, p0, pp, TX, lx, ly, Gx, Gy, Gz, lap);
+      CellState<R> c;
+      prologue(h, g, Gx, Gy, Gz, lap, a.P, c);
+      collide_g<R, MRT>(g, c, a.P);
+      collide_h<R, MRT>(h, c, a.P);
+      R phr[Q_H];
+      if (St::kShift) {
+        const R self = p0[opos];
+#pragma unroll
+        for (int i = 0; i < Q_H; ++i) {
+          const Dir d = ch(i);
+          const R* pl = d.z < 0 ? pm : (d.z > 0 ? pp : p0);
+          const R v = pl[(ly + 1 + d.y) * TX + (lx + 1 + d.x)];
+          phr[i] = (i == 0 || v == sentinel<R>()) ? self : v;
+        }
+        a.phi_out[idx] = self;
+      }
+      store_own<S, kNtStore>(a.h_out, a.g_out, G.N, idx, a.cd, phr, h, g);
+    }
   }
 }
 
 template <typename S>
 struct CellArgs {
   using R = typename Store<S>::R;
-  const S* h_in;             // populations read (== h, g for the in-place step)
+  const S* h_in;             // populations read
   const S* g_in;
-  S* h;                      // populations written
+  S* h;                      // populations written (AA step; == h_in in place)
   S* g;
   const R* phi;              // phi^n (stencil source)
-  const R* phi_prev;         // phi^{n-1} (writers of the populations read now)
+  const R* phi_prev;         // phi^{n-1} (FP16 shift references)
   const unsigned char* mask;
   Geom geo;
   Phys<R> P;
   Codec<R> cd;
-  // outputs of the moments mode (FP64, may be null)
-  double* out_phi;
+  double* out_phi;           // FP64 outputs of the moments kernel (may be null)
   double* out_u;
   double* out_p;
 };
 
-enum Mode { MODE_STEP = 0, MODE_MOMENTS = 1 };
+// AA cache policy (measured on the rising-bubble lattice, FP32): even steps
+// (own slots, aligned rows) stream with non-temporal loads and stores; odd
+// steps (neighbour slots, rows one element off alignment, lines shared by
+// neighbouring waves) use cached loads and non-temporal stores.
+template <bool ODD> struct AaPolicy {
+  static constexpr bool nt_load = !ODD;
+  static constexpr bool nt_store = true;
+};
 
-// Occupancy request of the fused kernel: 3 waves per SIMD (<= 168 VGPRs)
-// for the FP32-arithmetic forms, measured faster than the unconstrained 2;
-// the FP64 form keeps the compiler's choice (forcing it spills).
-template <typename S>
-struct StepWaves { static constexpr int value = sizeof(S) == 8 ? 1 : 3; };
-
-// Fused collide + stream of both lattices (MODE_STEP), or the cell moments
-// with the same force prologue (MODE_MOMENTS).
-template <typename S, bool MRT, bool ODD, bool MASK, int MODE>
+// In-place AA collide-and-stream of both lattices for one plane of one tile
+// (phi^n and, for FP16 storage, phi^{n-1} staged in LDS).  Also runs out of
+// place (h_in != h) between saved states.
+template <typename S, bool MRT, bool ODD, bool MASK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<S>::value)))
-void k_cell(CellArgs<S> a) {
+void k_cell_aa(CellArgs<S> a) {
   using R = typename Store<S>::R;
   extern __shared__ unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
@@ -400,56 +720,63 @@ void k_cell(CellArgs<S> a) {
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
   if (x >= G.nx || y >= G.ny) return;
-  const long long idx = x + (long long)G.nx * (y + (long long)G.ny * z);
-  if (tile[(TY + ly + 1) * TX + lx + 1] == sentinel<R>()) {   // solid cell
-    if (MODE == MODE_MOMENTS) {
-      if (a.out_phi) a.out_phi[idx] = 0.0;
-      if (a.out_p) a.out_p[idx] = 0.0;
-      if (a.out_u) { a.out_u[idx] = 0.0; a.out_u[G.N + idx] = 0.0; a.out_u[2 * G.N + idx] = 0.0; }
-    }
-    return;
-  }
+  const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
+  const R self = tile[(TY + ly + 1) * TX + lx + 1];
+  if (self == sentinel<R>()) return;   // solid cell
   const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
   const Nbhd nb = make_nbhd(x, y, z, G);
-  R phw[Q_H];
-  if (Store<S>::kShift) writer_phi_tile(tile_prev, TX, TY, lx, ly, walls, phw);
+  R ref[Q_H];
+  if (Store<S>::kShift) writer_refs_tile(tile_prev, TX, TY, lx, ly, walls, ref);
   R h[Q_H], g[Q_G];
-  load_pops<S, ODD>(a.h_in, a.g_in, G.N, (unsigned)idx, nb, walls, a.cd, phw, h, g);
+  load_pops<S, ODD ? RULE_AA_ODD : RULE_AA_EVEN, AaPolicy<ODD>::nt_load>(a.h_in, a.g_in, G.N, idx, nb, walls,
+                                                                        a.cd, ref, h, g);
   R Gx, Gy, Gz, lap;
   stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
   CellState<R> c;
   prologue(h, g, Gx, Gy, Gz, lap, a.P, c);
-  if (MODE == MODE_MOMENTS) {
-    if (a.out_phi) a.out_phi[idx] = double(c.phi);
-    if (a.out_p) a.out_p[idx] = double(c.p);
-    if (a.out_u) {
-      a.out_u[idx] = double(c.ux);
-      a.out_u[G.N + idx] = double(c.uy);
-      a.out_u[2 * G.N + idx] = double(c.uz);
-    }
-    return;
-  }
   collide_g<R, MRT>(g, c, a.P);
   collide_h<R, MRT>(h, c, a.P);
-  store_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd,
-                    tile[(TY + ly + 1) * TX + lx + 1], h, g);
+  store_aa<S, ODD, AaPolicy<ODD>::nt_store>(a.h, a.g, G.N, idx, nb, walls, a.cd, self, h, g);
 }
 
-// Neighbour-is-wall bits for the populations of one cell, without LDS
-// (used by the light kernels: gather, readout, reductions).
-template <bool MASK>
-__device__ __forceinline__ unsigned wall_bits_direct(int x, int y, int z, const Geom& G,
-                                                     const unsigned char* __restrict__ mask) {
-  unsigned b = 0;
-#pragma unroll
-  for (int k = 1; k < 27; ++k) {
-    const Dir d = cg(k);
-    int X = x + d.x, Y = y + d.y, Z = z + d.z;
-    bool ok = wrap(X, G.nx, G.px) && wrap(Y, G.ny, G.py) && wrap(Z, G.nz, G.pz);
-    if (ok && MASK) ok = !mask[X + (long long)G.nx * (Y + (long long)G.ny * Z)];
-    if (!ok) b |= 1u << k;
+// Cell moments phi, u, p* of the current state with the step's force
+// prologue (one plane per block, phi^n from the stored field).
+template <typename S, int RULE, bool MASK>
+__global__ __launch_bounds__(256) void k_moments(CellArgs<S> a) {
+  using R = typename Store<S>::R;
+  extern __shared__ unsigned char smem_raw[];
+  R* tile = reinterpret_cast<R*>(smem_raw);
+  const Geom& G = a.geo;
+  const int TX = G.bx + 2, TY = G.by + 2;
+  const TileCoord t = tile_of_block(G);
+  load_phi_tile<R, MASK>(tile, a.phi, a.mask, G, t);
+  __syncthreads();
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
+  if (tile[(TY + ly + 1) * TX + lx + 1] == sentinel<R>()) {   // solid cell
+    if (a.out_phi) a.out_phi[idx] = 0.0;
+    if (a.out_p) a.out_p[idx] = 0.0;
+    if (a.out_u) { a.out_u[idx] = 0.0; a.out_u[G.N + idx] = 0.0; a.out_u[2 * G.N + idx] = 0.0; }
+    return;
   }
-  return b;
+  const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
+  const Nbhd nb = make_nbhd(x, y, z, G);
+  R ref[Q_H], h[Q_H], g[Q_G];
+  shift_refs<S, RULE>(a.phi_prev, idx, nb, walls, ref);
+  load_pops<S, RULE, false>(a.h_in, a.g_in, G.N, idx, nb, walls, a.cd, ref, h, g);
+  R Gx, Gy, Gz, lap;
+  stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
+  CellState<R> c;
+  prologue(h, g, Gx, Gy, Gz, lap, a.P, c);
+  if (a.out_phi) a.out_phi[idx] = double(c.phi);
+  if (a.out_p) a.out_p[idx] = double(c.p);
+  if (a.out_u) {
+    a.out_u[idx] = double(c.ux);
+    a.out_u[G.N + idx] = double(c.uy);
+    a.out_u[2 * G.N + idx] = double(c.uz);
+  }
 }
 
 template <typename S>
@@ -457,22 +784,21 @@ struct LightArgs {
   using R = typename Store<S>::R;
   const S* h;
   const S* g;
-  const unsigned char* mask;
-  const R* phi_writers;  // phase field of the writers of the populations read
+  const unsigned* nbr;
+  const R* phi_prev;   // phi^{n-1} of the state read (FP16 shift references)
   Geom geo;
   Codec<R> cd;
   R* phi_out;          // gather target (compute precision)
   double* out_h;       // natural-order FP64 populations
   double* out_g;
-  double* out_phi64;   // FP64 phi
   double* partials;    // [nblocks][5]
 };
 
 enum LightMode { LM_GATHER = 0, LM_READ_POPS = 1, LM_REDUCE = 2 };
 
-// phi gather (phi = sum h with the read rule of the next step), population
-// readout, or per-block FP64 sums.
-template <typename S, bool ODD, bool MASK, int LM>
+// phi = sum of the h populations the next step reads (the state's phase
+// field), population readout, or per-block FP64 sums.
+template <typename S, int RULE, bool MASK, int LM>
 __global__ __launch_bounds__(256) void k_light(LightArgs<S> a) {
   using R = typename Store<S>::R;
   const Geom& G = a.geo;
@@ -481,8 +807,9 @@ __global__ __launch_bounds__(256) void k_light(LightArgs<S> a) {
   const bool in = x < G.nx && y < G.ny;
   double acc[5] = {0, 0, 0, 0, 0};
   if (in) {
-    const long long idx = x + (long long)G.nx * (y + (long long)G.ny * z);
-    const bool solid = MASK && a.mask[idx];
+    const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
+    bool solid;
+    const unsigned walls = cell_walls<MASK>(x, y, z, idx, G, a.nbr, solid);
     if (solid) {
       if (LM == LM_GATHER) a.phi_out[idx] = R(0);
       if (LM == LM_READ_POPS) {
@@ -490,32 +817,14 @@ __global__ __launch_bounds__(256) void k_light(LightArgs<S> a) {
         for (int i = 0; i < Q_G; ++i) a.out_g[i * G.N + idx] = 0.0;
       }
     } else {
-      const unsigned walls =
-          (ODD || Store<S>::kShift) ? wall_bits_direct<MASK>(x, y, z, G, a.mask) : 0u;
       const Nbhd nb = make_nbhd(x, y, z, G);
-      R phw[Q_H];
-      if (Store<S>::kShift) writer_phi_direct(a.phi_writers, (unsigned)idx, nb, walls, phw);
-      R h[Q_H], g[Q_G];
+      R ref[Q_H], h[Q_H], g[Q_G];
+      shift_refs<S, RULE>(a.phi_prev, idx, nb, walls, ref);
       if (LM == LM_GATHER) {
-        using St = Store<S>;
-        const unsigned NS = (unsigned)(G.N * (long long)sizeof(S));
-#pragma unroll
-        for (int i = 0; i < Q_H; ++i) {
-          unsigned off = pair_off<S>(i, (unsigned)idx, NS);
-          if (ODD && i) {
-            const Dir d = ch(i);
-            if (!(walls & (1u << nb27(-d.x, -d.y, -d.z))))
-              off = pair_off<S>(opp(i), nb.at(-d.x, -d.y, -d.z), NS);
-          }
-          const S* p = reinterpret_cast<const S*>(pair_base(a.h, G.N, i) + off);
-          h[i] = St::template ld<kNtGather>(p, St::kShift ? R(wh(i)) * phw[i] : R(0),
-                                                  a.cd.inv_scale_h);
-        }
-        const R s = sum_h(h);
-        a.phi_out[idx] = s;
-        if (a.out_phi64) a.out_phi64[idx] = double(s);
+        load_h<S, RULE, false>(a.h, G.N, idx, nb, walls, a.cd, ref, h);
+        a.phi_out[idx] = sum_h(h);
       } else {
-        load_pops<S, ODD>(a.h, a.g, G.N, (unsigned)idx, nb, walls, a.cd, phw, h, g);
+        load_pops<S, RULE, false>(a.h, a.g, G.N, idx, nb, walls, a.cd, ref, h, g);
         if (LM == LM_READ_POPS) {
 #pragma unroll
           for (int i = 0; i < Q_H; ++i) a.out_h[i * G.N + idx] = double(h[i]);
@@ -586,22 +895,42 @@ __global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict_
   }
 }
 
+// Solid-neighbour bits from the mask (box faces are not included; the
+// kernels add them from the coordinates).
+__global__ __launch_bounds__(256) void k_nbr_bits(const unsigned char* __restrict__ mask, Geom G,
+                                                  unsigned* __restrict__ out) {
+  const long long i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= G.N) return;
+  const int x = int(i % G.nx), y = int((i / G.nx) % G.ny), z = int(i / ((long long)G.nx * G.ny));
+  unsigned b = mask[i] ? 1u : 0u;
+  for (int k = 1; k < 27; ++k) {
+    int X = x + kC27[k].x, Y = y + kC27[k].y, Z = z + kC27[k].z;
+    if (wrap(X, G.nx, G.px) && wrap(Y, G.ny, G.py) && wrap(Z, G.nz, G.pz) &&
+        mask[X + (long long)G.nx * (Y + (long long)G.ny * Z)])
+      b |= 1u << k;
+  }
+  out[i] = b;
+}
+
 template <typename S>
 struct InitArgs {
   using R = typename Store<S>::R;
   S* h;
   S* g;
-  const unsigned char* mask;
+  const unsigned* nbr;
   const double* phi0;
   const double* u0;      // may be null
   const double* p0;      // may be null
-  const R* phi_ref;      // R(phi0): the phase field the FP16 shifts refer to
+  const R* phi_ref;      // R(phi0): the FP16 shift reference of the initial state
   Geom geo;
   Codec<R> cd;
 };
 
-// Equilibrium initialisation in the natural layout (the even-step read rule).
-template <typename S, bool MASK>
+// Equilibrium initialisation: every fluid cell writes its equilibrium
+// populations where the first step reads them (two buffers: the pull slots;
+// AA: its own slots, the even-step rule), shifted for FP16 storage by the
+// reference that read will use.
+template <typename S, bool AA, bool MASK>
 __global__ __launch_bounds__(256) void k_init(InitArgs<S> a) {
   using R = typename Store<S>::R;
   using St = Store<S>;
@@ -609,33 +938,34 @@ __global__ __launch_bounds__(256) void k_init(InitArgs<S> a) {
   const TileCoord t = tile_of_block(G);
   const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y, z = t.z;
   if (x >= G.nx || y >= G.ny) return;
-  const long long idx = x + (long long)G.nx * (y + (long long)G.ny * z);
-  const bool solid = MASK && a.mask[idx];
-  const R phi = solid ? R(0) : R(a.phi0[idx]);
+  const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
+  bool solid;
+  const unsigned walls = cell_walls<MASK>(x, y, z, idx, G, a.nbr, solid);
+  if (solid) return;
+  const Nbhd nb = make_nbhd(x, y, z, G);
+  const R phi = R(a.phi0[idx]);
   R ux = R(0), uy = R(0), uz = R(0), p = R(0);
-  if (!solid && a.u0) { ux = R(a.u0[idx]); uy = R(a.u0[G.N + idx]); uz = R(a.u0[2 * G.N + idx]); }
-  if (!solid && a.p0) p = R(a.p0[idx]);
+  if (a.u0) { ux = R(a.u0[idx]); uy = R(a.u0[G.N + idx]); uz = R(a.u0[2 * G.N + idx]); }
+  if (a.p0) p = R(a.p0[idx]);
   const R base = R(1) - R(1.5) * (ux * ux + uy * uy + uz * uz);
-  // the natural layout is read with the even rule, whose writer of
-  // population i is x - c_i (or x at a wall): shift by that cell's phi0
-  R phw[Q_H];
-  if (St::kShift && !solid) {
-    const unsigned walls = wall_bits_direct<MASK>(x, y, z, G, a.mask);
-    writer_phi_direct(a.phi_ref, (unsigned)idx, make_nbhd(x, y, z, G), walls, phw);
-  }
+  constexpr int RULE = AA ? RULE_AA_EVEN : RULE_AB;
+  R ref[Q_H];
+  shift_refs<S, RULE>(a.phi_ref, idx, nb, walls, ref);
+  const unsigned NS = (unsigned)(G.N * (long long)sizeof(S));
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
     const R cu = dot(ch(i), ux, uy, uz);
     const R v = R(wh(i)) * phi * (base + cu * (R(3) + R(4.5) * cu));
-    const R sh = (St::kShift && !solid) ? R(wh(i)) * phw[i] : R(0);
-    St::st(a.h + (long long)i * G.N + idx, v, sh, a.cd.scale_h);
+    S* q = reinterpret_cast<S*>(pair_base(a.h, G.N, i) + read_off<S, false, RULE>(i, idx, nb, walls, NS));
+    St::st(q, v, St::kShift ? R(wh(i)) * ref[i] : R(0), a.cd.scale_h);
   }
   const R baseg = p - R(1.5) * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) {
     const R cu = dot(cg(i), ux, uy, uz);
     const R v = R(wg(i)) * (baseg + cu * (R(3) + R(4.5) * cu));
-    St::st(a.g + (long long)i * G.N + idx, v, R(0), a.cd.scale_g);
+    S* q = reinterpret_cast<S*>(pair_base(a.g, G.N, i) + read_off<S, true, RULE>(i, idx, nb, walls, NS));
+    St::st(q, v, R(0), a.cd.scale_g);
   }
 }
 

@@ -1,8 +1,8 @@
 // C ABI of the coupled phase-field LBM step (see include/pflbm.h).
 //
 // Host side: argument checking, workspace carving, kernel dispatch over the
-// compile-time variants (storage type x collision x AA parity x mask), and
-// the adjoint bookkeeping.  Every launch goes to the context's stream; the
+// compile-time variants (storage type x collision x mask), the bookkeeping of
+// the two population buffers and phase-field buffers, and the adjoint.  Every launch goes to the context's stream; the
 // library never allocates device memory.
 #include <hip/hip_runtime.h>
 
@@ -32,6 +32,7 @@ bool desc_ok(const pflbm_desc* d) {
   if (d->precision < 0 || d->precision > 2) return false;
   if (d->collision < 0 || d->collision > 1) return false;
   if (d->periodic > 7u) return false;
+  if (d->streaming < 0 || d->streaming > 1) return false;
   const long long N = (long long)d->nx * d->ny * d->nz;
   // population addressing uses 32-bit byte offsets within each opposite pair
   // of populations (and within the FP32/FP64 adjoint arrays of one population)
@@ -42,33 +43,58 @@ bool desc_ok(const pflbm_desc* d) {
 
 struct Layout {
   int bx, by, tiles_x, tiles_y;
-  unsigned nblocks;
+  int zc, nchunks;          // z-chunks of the marching step kernel
+  unsigned nblocks;         // one-plane kernels: tiles x nz
+  unsigned nblocks_step;    // step kernel: tiles x nchunks
   long long N;
-  size_t off_h, off_g, off_phi[2], off_mask, off_part, off_red, total;
+  size_t off_h[2], off_g[2], off_phi[2], off_mask, off_nbr, off_part, off_red, total;
   size_t bytes_h, bytes_g, bytes_phi;
 };
 
-Layout make_layout(const pflbm_desc* d) {
-  Layout L{};
+// Tile width of the one-thread-per-cell kernels (bx * by = 256) and the
+// number of blocks the step kernel aims for when it splits z into chunks
+// (each chunk re-derives two extra phi planes, so fewer, longer chunks cost
+// less; enough blocks keep all 256 CUs busy through the tail).
 #ifndef PFLBM_TILE_X
 #define PFLBM_TILE_X 64
 #endif
+#ifndef PFLBM_STEP_BLOCKS
+#define PFLBM_STEP_BLOCKS 2048
+#endif
+#ifndef PFLBM_MIN_ZC
+#define PFLBM_MIN_ZC 4
+#endif
+
+Layout make_layout(const pflbm_desc* d) {
+  Layout L{};
   L.bx = d->nx > 32 ? PFLBM_TILE_X : (d->nx > 16 ? 32 : 16);
   L.by = 256 / L.bx;
   L.tiles_x = (d->nx + L.bx - 1) / L.bx;
   L.tiles_y = (d->ny + L.by - 1) / L.by;
   L.nblocks = (unsigned)L.tiles_x * (unsigned)L.tiles_y * (unsigned)d->nz;
+  const long long tiles = (long long)L.tiles_x * L.tiles_y;
+  long long nch = (PFLBM_STEP_BLOCKS + tiles - 1) / tiles;
+  nch = nch < 1 ? 1 : (nch > d->nz ? d->nz : nch);
+  L.zc = (int)((d->nz + nch - 1) / nch);
+  if (L.zc < PFLBM_MIN_ZC) L.zc = PFLBM_MIN_ZC < d->nz ? PFLBM_MIN_ZC : d->nz;
+  L.nchunks = (d->nz + L.zc - 1) / L.zc;
+  L.nblocks_step = (unsigned)(tiles * L.nchunks);
   L.N = (long long)d->nx * d->ny * d->nz;
   const size_t ss = store_size(d->precision), rs = real_size(d->precision);
   L.bytes_h = (size_t)Q_H * L.N * ss;
   L.bytes_g = (size_t)Q_G * L.N * ss;
   L.bytes_phi = (size_t)L.N * rs;
   size_t o = 0;
-  L.off_h = o; o = align_up(o + L.bytes_h);
-  L.off_g = o; o = align_up(o + L.bytes_g);
+  const int nbuf = d->streaming == PFLBM_STREAM_AA ? 1 : 2;
+  for (int k = 0; k < nbuf; ++k) {
+    L.off_h[k] = o; o = align_up(o + L.bytes_h);
+    L.off_g[k] = o; o = align_up(o + L.bytes_g);
+  }
+  if (nbuf == 1) { L.off_h[1] = L.off_h[0]; L.off_g[1] = L.off_g[0]; }
   L.off_phi[0] = o; o = align_up(o + L.bytes_phi);
   L.off_phi[1] = o; o = align_up(o + L.bytes_phi);
   L.off_mask = o; if (d->has_mask) o = align_up(o + (size_t)L.N);
+  L.off_nbr = o; if (d->has_mask) o = align_up(o + (size_t)L.N * sizeof(unsigned));
   L.off_part = o; o = align_up(o + (size_t)L.nblocks * 8 * sizeof(double));
   L.off_red = o; o = align_up(o + 8 * sizeof(double));
   L.total = o;
@@ -107,7 +133,9 @@ struct pflbm_ctx {
   hipStream_t stream;
   Layout L;
   char* ws;
-  int cur = 0;
+  int pcur = 0;          // population buffer holding the current state
+  int iprev = 1;         // phi buffer holding phi^{n-1} (FP16 storage, AA)
+  bool phi_ok = false;   // phi^n of the current state has been gathered
   int64_t steps = 0;
   int64_t check_every = 0;
   bool initialised = false;
@@ -138,6 +166,8 @@ Geom make_geom(const pflbm_ctx* c) {
   G.bx = c->L.bx; G.by = c->L.by;
   G.tiles_x = c->L.tiles_x; G.tiles_y = c->L.tiles_y;
   G.nblocks = c->L.nblocks;
+  G.zc = c->L.zc; G.nchunks = c->L.nchunks;
+  G.nblocks_step = c->L.nblocks_step;
   G.N = c->L.N;
   return G;
 }
@@ -172,58 +202,135 @@ Codec<R> make_codec(const pflbm_ctx* c) {
   return cd;
 }
 
-template <typename S> S* pop_h(pflbm_ctx* c) { return reinterpret_cast<S*>(c->ws + c->L.off_h); }
-template <typename S> S* pop_g(pflbm_ctx* c) { return reinterpret_cast<S*>(c->ws + c->L.off_g); }
+bool shifted(const pflbm_ctx* c) { return c->d.precision == PFLBM_FP32_FP16S; }
+bool is_aa(const pflbm_ctx* c) { return c->d.streaming == PFLBM_STREAM_AA; }
+
+template <typename S> S* pop_h(pflbm_ctx* c, int k) { return reinterpret_cast<S*>(c->ws + c->L.off_h[k]); }
+template <typename S> S* pop_g(pflbm_ctx* c, int k) { return reinterpret_cast<S*>(c->ws + c->L.off_g[k]); }
 template <typename R> R* phi_buf(pflbm_ctx* c, int k) { return reinterpret_cast<R*>(c->ws + c->L.off_phi[k]); }
 unsigned char* mask_ptr(pflbm_ctx* c) {
   return c->d.has_mask ? reinterpret_cast<unsigned char*>(c->ws + c->L.off_mask) : nullptr;
 }
+unsigned* nbr_ptr(pflbm_ctx* c) {
+  return c->d.has_mask ? reinterpret_cast<unsigned*>(c->ws + c->L.off_nbr) : nullptr;
+}
+// phi buffer that holds (or receives) phi^n of the current state; the other
+// one holds phi^{n-1} where a step needs it (FP16 shifts, and the AA step,
+// which forms phi^{n+1} into it)
+int phi_cur_idx(const pflbm_ctx* c) { return (shifted(c) || is_aa(c)) ? (c->iprev ^ 1) : 0; }
+template <typename R> R* phi_cur(pflbm_ctx* c) { return phi_buf<R>(c, phi_cur_idx(c)); }
+template <typename R> R* phi_prev(pflbm_ctx* c) { return shifted(c) ? phi_buf<R>(c, c->iprev) : nullptr; }
+
+// A saved state: h, g, phi^n and, for FP16 storage, phi^{n-1}.
+struct StateView { size_t oh, og, ophi, oprev, total; };
+StateView state_view(const pflbm_ctx* c) {
+  StateView v;
+  v.oh = 0;
+  v.og = c->L.bytes_h;
+  v.ophi = c->L.bytes_h + c->L.bytes_g;
+  v.oprev = v.ophi + c->L.bytes_phi;
+  v.total = v.oprev + (shifted(c) ? c->L.bytes_phi : 0);
+  return v;
+}
 
 // ---- launch helpers ----------------------------------------------------------
-template <typename S, bool MRT, bool ODD, int MODE>
-void launch_cell_m(pflbm_ctx* c, const CellArgs<S>& a) {
+template <typename S>
+StepArgs<S> step_args(pflbm_ctx* c) {
   using R = typename Store<S>::R;
-  const size_t sm = (size_t)(c->L.bx + 2) * (c->L.by + 2) * 3 * sizeof(R) * (Store<S>::kShift ? 2 : 1);
-  const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
-  if (c->d.has_mask)
-    hipLaunchKernelGGL((k_cell<S, MRT, ODD, true, MODE>), grd, blk, sm, c->stream, a);
-  else
-    hipLaunchKernelGGL((k_cell<S, MRT, ODD, false, MODE>), grd, blk, sm, c->stream, a);
-}
-
-template <typename S, int MODE>
-void launch_cell(pflbm_ctx* c, const CellArgs<S>& a, bool odd) {
-  const bool mrt = c->d.collision == PFLBM_MRT;
-  if (mrt) {
-    if (odd) launch_cell_m<S, true, true, MODE>(c, a); else launch_cell_m<S, true, false, MODE>(c, a);
-  } else {
-    if (odd) launch_cell_m<S, false, true, MODE>(c, a); else launch_cell_m<S, false, false, MODE>(c, a);
-  }
-}
-
-template <typename S, int LM>
-void launch_light(pflbm_ctx* c, const LightArgs<S>& a, bool odd) {
-  const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
-  const bool m = c->d.has_mask;
-  if (odd) {
-    if (m) hipLaunchKernelGGL((k_light<S, true, true, LM>), grd, blk, 0, c->stream, a);
-    else hipLaunchKernelGGL((k_light<S, true, false, LM>), grd, blk, 0, c->stream, a);
-  } else {
-    if (m) hipLaunchKernelGGL((k_light<S, false, true, LM>), grd, blk, 0, c->stream, a);
-    else hipLaunchKernelGGL((k_light<S, false, false, LM>), grd, blk, 0, c->stream, a);
-  }
+  StepArgs<S> a;
+  a.h_in = pop_h<S>(c, c->pcur);
+  a.g_in = pop_g<S>(c, c->pcur);
+  a.h_out = pop_h<S>(c, c->pcur ^ 1);
+  a.g_out = pop_g<S>(c, c->pcur ^ 1);
+  a.phi_prev = phi_prev<R>(c);
+  a.phi_out = shifted(c) ? phi_buf<R>(c, c->iprev ^ 1) : nullptr;
+  a.nbr = nbr_ptr(c);
+  a.geo = make_geom(c);
+  a.P = make_phys<R>(c->p);
+  a.cd = make_codec<R>(c);
+  return a;
 }
 
 template <typename S>
-CellArgs<S> cell_args(pflbm_ctx* c) {
+void launch_step(pflbm_ctx* c, const StepArgs<S>& a) {
+  using R = typename Store<S>::R;
+  const size_t sm = (size_t)4 * (c->L.bx + 2) * (c->L.by + 2) * sizeof(R);
+  const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks_step);
+  const bool mrt = c->d.collision == PFLBM_MRT, m = c->d.has_mask;
+  if (mrt) {
+    if (m) hipLaunchKernelGGL((k_step<S, true, true>), grd, blk, sm, c->stream, a);
+    else hipLaunchKernelGGL((k_step<S, true, false>), grd, blk, sm, c->stream, a);
+  } else {
+    if (m) hipLaunchKernelGGL((k_step<S, false, true>), grd, blk, sm, c->stream, a);
+    else hipLaunchKernelGGL((k_step<S, false, false>), grd, blk, sm, c->stream, a);
+  }
+}
+
+// the state advanced by one step: buffers swap, phi^n becomes the shift
+// reference, phi^{n+1} is not gathered yet
+void advance(pflbm_ctx* c) {
+  c->pcur ^= 1;
+  if (shifted(c)) c->iprev ^= 1;
+  c->phi_ok = false;
+  c->steps += 1;
+}
+
+template <typename S>
+LightArgs<S> light_args(pflbm_ctx* c) {
+  using R = typename Store<S>::R;
+  LightArgs<S> a;
+  a.h = pop_h<S>(c, c->pcur);
+  a.g = pop_g<S>(c, c->pcur);
+  a.nbr = nbr_ptr(c);
+  a.phi_prev = phi_prev<R>(c);
+  a.geo = make_geom(c);
+  a.cd = make_codec<R>(c);
+  a.phi_out = nullptr;
+  a.out_h = a.out_g = nullptr;
+  a.partials = nullptr;
+  return a;
+}
+
+// read rule of a state after `steps` steps
+int state_rule(const pflbm_ctx* c, int64_t steps) {
+  return !is_aa(c) ? RULE_AB : ((steps & 1) ? RULE_AA_ODD : RULE_AA_EVEN);
+}
+
+template <typename S, int LM, int RULE>
+void launch_light_r(pflbm_ctx* c, const LightArgs<S>& a) {
+  const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
+  if (c->d.has_mask) hipLaunchKernelGGL((k_light<S, RULE, true, LM>), grd, blk, 0, c->stream, a);
+  else hipLaunchKernelGGL((k_light<S, RULE, false, LM>), grd, blk, 0, c->stream, a);
+}
+
+template <typename S, int LM>
+void launch_light(pflbm_ctx* c, const LightArgs<S>& a, int rule) {
+  if (rule == RULE_AB) launch_light_r<S, LM, RULE_AB>(c, a);
+  else if (rule == RULE_AA_ODD) launch_light_r<S, LM, RULE_AA_ODD>(c, a);
+  else launch_light_r<S, LM, RULE_AA_EVEN>(c, a);
+}
+
+// phi^n of the current state (sum of the h its next step reads), gathered on
+// demand
+template <typename S>
+void ensure_phi(pflbm_ctx* c) {
+  using R = typename Store<S>::R;
+  if (c->phi_ok) return;
+  LightArgs<S> a = light_args<S>(c);
+  a.phi_out = phi_cur<R>(c);
+  launch_light<S, LM_GATHER>(c, a, state_rule(c, c->steps));
+  c->phi_ok = true;
+}
+
+// ---- AA step ------------------------------------------------------------------
+template <typename S>
+CellArgs<S> aa_args(pflbm_ctx* c) {
   using R = typename Store<S>::R;
   CellArgs<S> a;
-  a.h = pop_h<S>(c);
-  a.g = pop_g<S>(c);
-  a.h_in = a.h;
-  a.g_in = a.g;
-  a.phi = phi_buf<R>(c, c->cur);
-  a.phi_prev = phi_buf<R>(c, c->cur ^ 1);
+  a.h_in = a.h = pop_h<S>(c, 0);
+  a.g_in = a.g = pop_g<S>(c, 0);
+  a.phi = phi_cur<R>(c);
+  a.phi_prev = phi_prev<R>(c);
   a.mask = mask_ptr(c);
   a.geo = make_geom(c);
   a.P = make_phys<R>(c->p);
@@ -232,32 +339,50 @@ CellArgs<S> cell_args(pflbm_ctx* c) {
   return a;
 }
 
-template <typename S>
-LightArgs<S> light_args(pflbm_ctx* c) {
+template <typename S, bool MRT, bool ODD>
+void launch_aa_m(pflbm_ctx* c, const CellArgs<S>& a) {
   using R = typename Store<S>::R;
-  LightArgs<S> a;
-  a.h = pop_h<S>(c);
-  a.g = pop_g<S>(c);
-  a.mask = mask_ptr(c);
-  a.phi_writers = phi_buf<R>(c, c->cur ^ 1);   // writers of the current state: phi^{n-1}
-  a.geo = make_geom(c);
-  a.cd = make_codec<R>(c);
-  a.phi_out = nullptr;
-  a.out_h = a.out_g = a.out_phi64 = nullptr;
-  a.partials = nullptr;
-  return a;
+  const size_t sm = (size_t)(c->L.bx + 2) * (c->L.by + 2) * 3 * sizeof(R) * (Store<S>::kShift ? 2 : 1);
+  const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
+  if (c->d.has_mask) hipLaunchKernelGGL((k_cell_aa<S, MRT, ODD, true>), grd, blk, sm, c->stream, a);
+  else hipLaunchKernelGGL((k_cell_aa<S, MRT, ODD, false>), grd, blk, sm, c->stream, a);
 }
 
-// phi = sum h with the read rule of the step the counter points at, into
-// buffer `target`; the populations were written by cells whose phi is in the
-// other buffer
 template <typename S>
-void gather_phi(pflbm_ctx* c, int target) {
+void launch_aa(pflbm_ctx* c, const CellArgs<S>& a, bool odd) {
+  if (c->d.collision == PFLBM_MRT) {
+    if (odd) launch_aa_m<S, true, true>(c, a); else launch_aa_m<S, true, false>(c, a);
+  } else {
+    if (odd) launch_aa_m<S, false, true>(c, a); else launch_aa_m<S, false, false>(c, a);
+  }
+}
+
+// phi^{n+1} after an AA step, into the buffer of phi^{n-1}; the writers'
+// phase field phi^n becomes the shift reference
+template <typename S>
+void aa_gather(pflbm_ctx* c) {
   using R = typename Store<S>::R;
   LightArgs<S> a = light_args<S>(c);
-  a.phi_out = phi_buf<R>(c, target);
-  a.phi_writers = phi_buf<R>(c, target ^ 1);
-  launch_light<S, LM_GATHER>(c, a, c->steps & 1);
+  a.phi_prev = phi_buf<R>(c, c->iprev ^ 1);
+  a.phi_out = phi_buf<R>(c, c->iprev);
+  launch_light<S, LM_GATHER>(c, a, state_rule(c, c->steps));
+  c->iprev ^= 1;
+  c->phi_ok = true;
+}
+
+// one step of the context's state with either scheme; the AA phi pass is
+// timed separately when events are given
+template <typename S>
+void one_step(pflbm_ctx* c, hipEvent_t mid = nullptr) {
+  if (!is_aa(c)) {
+    launch_step<S>(c, step_args<S>(c));
+    advance(c);
+    return;
+  }
+  launch_aa<S>(c, aa_args<S>(c), c->steps & 1);
+  if (mid) hipEventRecord(mid, c->stream);
+  c->steps += 1;
+  aa_gather<S>(c);
 }
 
 template <typename S>
@@ -266,11 +391,7 @@ pflbm_status do_reduce(pflbm_ctx* c, double* out_host);
 template <typename S>
 pflbm_status do_steps(pflbm_ctx* c, int64_t n) {
   for (int64_t s = 0; s < n; ++s) {
-    CellArgs<S> a = cell_args<S>(c);
-    launch_cell<S, MODE_STEP>(c, a, c->steps & 1);
-    c->steps += 1;
-    gather_phi<S>(c, c->cur ^ 1);
-    c->cur ^= 1;
+    one_step<S>(c);
     if (c->check_every > 0 && c->steps % c->check_every == 0) {
       double r[5];
       const pflbm_status st = do_reduce<S>(c, r);
@@ -283,30 +404,54 @@ pflbm_status do_steps(pflbm_ctx* c, int64_t n) {
 }
 
 // One step from a saved state (level n) into another saved-state buffer
-// (level n + 1), leaving the context's own state untouched.  Out of place is
-// valid for the AA pattern because each step writes every slot exactly once.
+// (level n + 1), leaving the context's own state untouched.
+//   AB: the step kernel writes dst's populations (and, for FP16 storage,
+//       phi^n as dst's shift reference), then phi^{n+1} is gathered into dst.
+//   AA: the collide-and-stream kernel runs out of place (each slot is written
+//       exactly once, so dst needs no copy of src), phi^{n+1} is gathered with
+//       the writers' phi^n from src, and src's phi^n becomes dst's reference.
 template <typename S>
 pflbm_status do_step_states(pflbm_ctx* c, const void* src, void* dst, int64_t n) {
   using R = typename Store<S>::R;
   const char* s = static_cast<const char*>(src);
   char* d = static_cast<char*>(dst);
-  const size_t oh = 0, og = c->L.bytes_h, op = c->L.bytes_h + c->L.bytes_g, oq = op + c->L.bytes_phi;
-  CellArgs<S> a = cell_args<S>(c);
-  a.h_in = reinterpret_cast<const S*>(s + oh);
-  a.g_in = reinterpret_cast<const S*>(s + og);
-  a.h = reinterpret_cast<S*>(d + oh);
-  a.g = reinterpret_cast<S*>(d + og);
-  a.phi = reinterpret_cast<const R*>(s + op);
-  a.phi_prev = reinterpret_cast<const R*>(s + oq);
-  launch_cell<S, MODE_STEP>(c, a, n & 1);
+  const StateView v = state_view(c);
+  const S* hs = reinterpret_cast<const S*>(s + v.oh);
+  const S* gs = reinterpret_cast<const S*>(s + v.og);
+  S* hd = reinterpret_cast<S*>(d + v.oh);
+  S* gd = reinterpret_cast<S*>(d + v.og);
   LightArgs<S> b = light_args<S>(c);
-  b.h = a.h;
-  b.g = a.g;
-  b.phi_writers = reinterpret_cast<const R*>(s + op);
-  b.phi_out = reinterpret_cast<R*>(d + op);
-  launch_light<S, LM_GATHER>(c, b, (n + 1) & 1);
-  hipError_t e = hipMemcpyAsync(d + oq, s + op, c->L.bytes_phi, hipMemcpyDeviceToDevice, c->stream);
-  if (e != hipSuccess) return check_hip(c, e, "pflbm_step_states copy");
+  b.h = hd;
+  b.g = gd;
+  b.phi_out = reinterpret_cast<R*>(d + v.ophi);
+  if (!is_aa(c)) {
+    StepArgs<S> a = step_args<S>(c);
+    a.h_in = hs;
+    a.g_in = gs;
+    a.h_out = hd;
+    a.g_out = gd;
+    a.phi_prev = shifted(c) ? reinterpret_cast<const R*>(s + v.oprev) : nullptr;
+    a.phi_out = shifted(c) ? reinterpret_cast<R*>(d + v.oprev) : nullptr;
+    launch_step<S>(c, a);
+    b.phi_prev = a.phi_out;
+    launch_light<S, LM_GATHER>(c, b, RULE_AB);
+  } else {
+    CellArgs<S> a = aa_args<S>(c);
+    a.h_in = hs;
+    a.g_in = gs;
+    a.h = hd;
+    a.g = gd;
+    a.phi = reinterpret_cast<const R*>(s + v.ophi);
+    a.phi_prev = shifted(c) ? reinterpret_cast<const R*>(s + v.oprev) : nullptr;
+    launch_aa<S>(c, a, n & 1);
+    b.phi_prev = a.phi;
+    launch_light<S, LM_GATHER>(c, b, state_rule(c, n + 1));
+    if (shifted(c)) {
+      const hipError_t e = hipMemcpyAsync(d + v.oprev, s + v.ophi, c->L.bytes_phi, hipMemcpyDeviceToDevice,
+                                          c->stream);
+      if (e != hipSuccess) return check_hip(c, e, "pflbm_step_states copy");
+    }
+  }
   return check_hip(c, hipGetLastError(), "pflbm_step_states");
 }
 
@@ -318,12 +463,8 @@ pflbm_status do_profile(pflbm_ctx* c, int64_t n, double* out_ms) {
     if (pflbm_status s = check_hip(c, hipEventCreate(&e), "pflbm_profile_step event")) return s;
   hipEventRecord(ev[0], c->stream);
   for (int64_t s = 0; s < n; ++s) {
-    CellArgs<S> a = cell_args<S>(c);
-    launch_cell<S, MODE_STEP>(c, a, c->steps & 1);
-    hipEventRecord(ev[2 * s + 1], c->stream);
-    c->steps += 1;
-    gather_phi<S>(c, c->cur ^ 1);
-    c->cur ^= 1;
+    one_step<S>(c, ev[2 * s + 1]);
+    if (!is_aa(c)) hipEventRecord(ev[2 * s + 1], c->stream);
     hipEventRecord(ev[2 * s + 2], c->stream);
   }
   pflbm_status st = check_hip(c, hipEventSynchronize(ev[2 * n]), "pflbm_profile_step");
@@ -349,38 +490,72 @@ pflbm_status do_profile(pflbm_ctx* c, int64_t n, double* out_ms) {
 template <typename S>
 pflbm_status do_init(pflbm_ctx* c, const double* phi0, const double* u0, const double* p0) {
   using R = typename Store<S>::R;
+  c->pcur = 0;
+  c->iprev = 1;
   InitArgs<S> a;
-  a.h = pop_h<S>(c);
-  a.g = pop_g<S>(c);
-  a.mask = mask_ptr(c);
+  a.h = pop_h<S>(c, 0);
+  a.g = pop_g<S>(c, 0);
+  a.nbr = nbr_ptr(c);
   a.phi0 = phi0;
   a.u0 = u0;
   a.p0 = p0;
-  a.phi_ref = phi_buf<R>(c, 1);
+  a.phi_ref = phi_prev<R>(c);
   a.geo = make_geom(c);
   a.cd = make_codec<R>(c);
-  // buffer 1 takes R(phi0): the reference of the FP16 shifts of the initial
-  // populations (it plays phi^{-1}); buffer 0 then receives phi^0 = sum h^0
-  const unsigned nb = (unsigned)((c->L.N + 255) / 256);
-  hipLaunchKernelGGL(k_phi_from_f64<R>, dim3(nb), dim3(256), 0, c->stream, phi0, mask_ptr(c), c->L.N,
-                     phi_buf<R>(c, 1));
+  // FP16 storage: R(phi0) plays phi^{-1}, the shift reference of the initial
+  // populations
+  if (shifted(c)) {
+    const unsigned nb = (unsigned)((c->L.N + 255) / 256);
+    hipLaunchKernelGGL(k_phi_from_f64<R>, dim3(nb), dim3(256), 0, c->stream, phi0, mask_ptr(c), c->L.N,
+                       phi_buf<R>(c, c->iprev));
+  }
   const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
-  if (c->d.has_mask) hipLaunchKernelGGL((k_init<S, true>), grd, blk, 0, c->stream, a);
-  else hipLaunchKernelGGL((k_init<S, false>), grd, blk, 0, c->stream, a);
+  const bool m = c->d.has_mask;
+  if (is_aa(c)) {
+    if (m) hipLaunchKernelGGL((k_init<S, true, true>), grd, blk, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_init<S, true, false>), grd, blk, 0, c->stream, a);
+  } else {
+    if (m) hipLaunchKernelGGL((k_init<S, false, true>), grd, blk, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_init<S, false, false>), grd, blk, 0, c->stream, a);
+  }
   c->steps = 0;
-  c->cur = 0;
-  gather_phi<S>(c, 0);
+  c->phi_ok = false;
+  ensure_phi<S>(c);
   return check_hip(c, hipGetLastError(), "pflbm_init_equilibrium");
+}
+
+template <typename S, int RULE>
+void launch_moments(pflbm_ctx* c, const CellArgs<S>& a) {
+  using R = typename Store<S>::R;
+  const size_t sm = (size_t)(c->L.bx + 2) * (c->L.by + 2) * 3 * sizeof(R);
+  const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
+  if (c->d.has_mask) hipLaunchKernelGGL((k_moments<S, RULE, true>), grd, blk, sm, c->stream, a);
+  else hipLaunchKernelGGL((k_moments<S, RULE, false>), grd, blk, sm, c->stream, a);
 }
 
 template <typename S>
 pflbm_status do_moments(pflbm_ctx* c, double* phi, double* u, double* p) {
-  CellArgs<S> a = cell_args<S>(c);
+  ensure_phi<S>(c);
+  CellArgs<S> a = aa_args<S>(c);
+  a.h_in = pop_h<S>(c, c->pcur);
+  a.g_in = pop_g<S>(c, c->pcur);
   a.out_phi = phi;
   a.out_u = u;
   a.out_p = p;
-  launch_cell<S, MODE_MOMENTS>(c, a, c->steps & 1);
+  const int rule = state_rule(c, c->steps);
+  if (rule == RULE_AB) launch_moments<S, RULE_AB>(c, a);
+  else if (rule == RULE_AA_ODD) launch_moments<S, RULE_AA_ODD>(c, a);
+  else launch_moments<S, RULE_AA_EVEN>(c, a);
   return check_hip(c, hipGetLastError(), "pflbm_read_moments");
+}
+
+template <typename S>
+pflbm_status do_read_phi(pflbm_ctx* c, double* d_phi) {
+  using R = typename Store<S>::R;
+  ensure_phi<S>(c);
+  const unsigned nb = (unsigned)((c->L.N + 255) / 256);
+  hipLaunchKernelGGL(k_phi_to_f64<R>, dim3(nb), dim3(256), 0, c->stream, phi_cur<R>(c), c->L.N, d_phi);
+  return check_hip(c, hipGetLastError(), "pflbm_read_phi");
 }
 
 template <typename S>
@@ -388,8 +563,24 @@ pflbm_status do_read_pops(pflbm_ctx* c, double* h, double* g) {
   LightArgs<S> a = light_args<S>(c);
   a.out_h = h;
   a.out_g = g;
-  launch_light<S, LM_READ_POPS>(c, a, c->steps & 1);
+  launch_light<S, LM_READ_POPS>(c, a, state_rule(c, c->steps));
   return check_hip(c, hipGetLastError(), "pflbm_read_populations");
+}
+
+template <typename S>
+pflbm_status do_save_state(pflbm_ctx* c, void* dst) {
+  using R = typename Store<S>::R;
+  ensure_phi<S>(c);
+  char* o = static_cast<char*>(dst);
+  const StateView v = state_view(c);
+  hipError_t e = hipMemcpyAsync(o + v.oh, pop_h<S>(c, c->pcur), c->L.bytes_h, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o + v.og, pop_g<S>(c, c->pcur), c->L.bytes_g, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o + v.ophi, phi_cur<R>(c), c->L.bytes_phi, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && shifted(c))
+    e = hipMemcpyAsync(o + v.oprev, phi_prev<R>(c), c->L.bytes_phi, hipMemcpyDeviceToDevice, c->stream);
+  return check_hip(c, e, "pflbm_save_state");
 }
 
 template <typename S>
@@ -398,7 +589,7 @@ pflbm_status do_reduce(pflbm_ctx* c, double* out_host) {
   double* part = reinterpret_cast<double*>(c->ws + c->L.off_part);
   double* red = reinterpret_cast<double*>(c->ws + c->L.off_red);
   a.partials = part;
-  launch_light<S, LM_REDUCE>(c, a, c->steps & 1);
+  launch_light<S, LM_REDUCE>(c, a, state_rule(c, c->steps));
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->stream, part, c->L.nblocks, 5, red);
   pflbm_status s = check_hip(c, hipGetLastError(), "pflbm_reduce launch");
   if (s) return s;
@@ -501,6 +692,10 @@ pflbm_status pflbm_set_mask(pflbm_ctx* c, const uint8_t* d_solid) {
   if (!d_solid) return fail(c, PFLBM_ERR_ARG, "mask pointer is NULL");
   pflbm_status s = check_hip(c, hipMemcpyAsync(mask_ptr(c), d_solid, (size_t)c->L.N,
                                                hipMemcpyDeviceToDevice, c->stream), "pflbm_set_mask");
+  if (s) return s;
+  const unsigned nb = (unsigned)((c->L.N + 255) / 256);
+  hipLaunchKernelGGL(k_nbr_bits, dim3(nb), dim3(256), 0, c->stream, mask_ptr(c), make_geom(c), nbr_ptr(c));
+  s = check_hip(c, hipGetLastError(), "pflbm_set_mask");
   if (!s) c->mask_set = true;
   return s;
 }
@@ -545,14 +740,7 @@ pflbm_status pflbm_read_phi(pflbm_ctx* c, double* d_phi) {
   if (!c) return PFLBM_ERR_ARG;
   if (!d_phi) return fail(c, PFLBM_ERR_ARG, "output is NULL");
   if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
-  const unsigned nb = (unsigned)((c->L.N + 255) / 256);
-  if (c->d.precision == PFLBM_FP64)
-    hipLaunchKernelGGL(k_phi_to_f64<double>, dim3(nb), dim3(256), 0, c->stream,
-                       phi_buf<double>(c, c->cur), c->L.N, d_phi);
-  else
-    hipLaunchKernelGGL(k_phi_to_f64<float>, dim3(nb), dim3(256), 0, c->stream,
-                       phi_buf<float>(c, c->cur), c->L.N, d_phi);
-  return check_hip(c, hipGetLastError(), "pflbm_read_phi");
+  DISPATCH(c, do_read_phi, c, d_phi);
 }
 
 pflbm_status pflbm_read_populations(pflbm_ctx* c, double* h, double* g) {
@@ -571,25 +759,14 @@ pflbm_status pflbm_reduce(pflbm_ctx* c, double out_host[5]) {
 
 size_t pflbm_state_bytes(const pflbm_ctx* c) {
   if (!c) return 0;
-  return c->L.bytes_h + c->L.bytes_g + 2 * c->L.bytes_phi;
+  return state_view(c).total;
 }
 
 pflbm_status pflbm_save_state(pflbm_ctx* c, void* dst) {
   if (!c) return PFLBM_ERR_ARG;
   if (!dst) return fail(c, PFLBM_ERR_ARG, "destination is NULL");
   if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
-  char* o = static_cast<char*>(dst);
-  hipError_t e = hipMemcpyAsync(o, c->ws + c->L.off_h, c->L.bytes_h, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(o + c->L.bytes_h, c->ws + c->L.off_g, c->L.bytes_g, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(o + c->L.bytes_h + c->L.bytes_g, c->ws + c->L.off_phi[c->cur], c->L.bytes_phi,
-                       hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(o + c->L.bytes_h + c->L.bytes_g + c->L.bytes_phi,
-                       c->ws + c->L.off_phi[c->cur ^ 1], c->L.bytes_phi, hipMemcpyDeviceToDevice,
-                       c->stream);
-  return check_hip(c, e, "pflbm_save_state");
+  DISPATCH(c, do_save_state, c, dst);
 }
 
 pflbm_status pflbm_load_state(pflbm_ctx* c, const void* src, int64_t step_count) {
@@ -597,16 +774,19 @@ pflbm_status pflbm_load_state(pflbm_ctx* c, const void* src, int64_t step_count)
   if (!src || step_count < 0) return fail(c, PFLBM_ERR_ARG, "bad source or step count");
   if (c->d.has_mask && !c->mask_set) return fail(c, PFLBM_ERR_STATE, "mask not set");
   const char* o = static_cast<const char*>(src);
-  hipError_t e = hipMemcpyAsync(c->ws + c->L.off_h, o, c->L.bytes_h, hipMemcpyDeviceToDevice, c->stream);
+  const StateView v = state_view(c);
+  c->pcur = 0;
+  c->iprev = 1;
+  hipError_t e = hipMemcpyAsync(c->ws + c->L.off_h[0], o + v.oh, c->L.bytes_h, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(c->ws + c->L.off_g, o + c->L.bytes_h, c->L.bytes_g, hipMemcpyDeviceToDevice, c->stream);
+    e = hipMemcpyAsync(c->ws + c->L.off_g[0], o + v.og, c->L.bytes_g, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(c->ws + c->L.off_phi[0], o + c->L.bytes_h + c->L.bytes_g, c->L.bytes_phi,
+    e = hipMemcpyAsync(c->ws + c->L.off_phi[phi_cur_idx(c)], o + v.ophi, c->L.bytes_phi,
                        hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(c->ws + c->L.off_phi[1], o + c->L.bytes_h + c->L.bytes_g + c->L.bytes_phi,
-                       c->L.bytes_phi, hipMemcpyDeviceToDevice, c->stream);
-  c->cur = 0;
+  if (e == hipSuccess && shifted(c))
+    e = hipMemcpyAsync(c->ws + c->L.off_phi[c->iprev], o + v.oprev, c->L.bytes_phi, hipMemcpyDeviceToDevice,
+                       c->stream);
+  c->phi_ok = true;
   c->steps = step_count;
   c->initialised = true;
   return check_hip(c, e, "pflbm_load_state");

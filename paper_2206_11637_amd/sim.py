@@ -49,7 +49,7 @@ class Simulation:
 
     def __init__(self, nx: int, ny: int, nz: int, periodic=(True, False, True),
                  precision: str = "fp32", collision: str = "mrt", solid=None, params=None,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", streaming: str = "ab"):
         self.lib = load()
         self.device = torch.device(device)
         self.shape = (nz, ny, nx)
@@ -57,7 +57,8 @@ class Simulation:
         self.precision = precision
         pbits = int(bool(periodic[0])) | (int(bool(periodic[1])) << 1) | (int(bool(periodic[2])) << 2)
         self.desc = Desc(nx, ny, nz, pbits, _lib.PRECISIONS[precision],
-                         _lib.COLLISIONS[collision], int(solid is not None))
+                         _lib.COLLISIONS[collision], int(solid is not None),
+                         _lib.STREAMING[streaming])
         nbytes = self.lib.pflbm_workspace_bytes(C.byref(self.desc))
         if nbytes == 0:
             raise ValueError(f"invalid lattice description {nx}x{ny}x{nz}")
@@ -203,9 +204,11 @@ class Simulation:
         return float(out[0]), float(out[1])
 
 
-def from_workload(wl, precision="fp32", collision="mrt", device="cuda:0", params=None) -> Simulation:
-    """Simulation for a workloads.Workload, initialised at equilibrium."""
+def from_workload(wl, precision="fp32", collision="mrt", device="cuda:0", params=None,
+                  streaming="ab") -> Simulation:
+    """Simulation for a workloads.Workload, initialised at equilibrium.
+    streaming: "ab" (two buffers, fused step) or "aa" (in place)."""
     sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, precision, collision, wl.solid,
-                     params if params is not None else wl.params, device)
+                     params if params is not None else wl.params, device, streaming)
     sim.init_equilibrium(wl.phi0, wl.u0, wl.pstar0)
     return sim

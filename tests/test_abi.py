@@ -43,10 +43,14 @@ def test_workspace_sizes_and_invalid_descriptions():
     assert n64 >= (42 * 8 + 2 * 8) * N
     d32 = L.Desc(32, 32, 32, 5, 1, 1, 0)
     d16 = L.Desc(32, 32, 32, 5, 2, 1, 1)
-    assert lib.pflbm_workspace_bytes(C.byref(d32)) >= (42 * 4 + 8) * N
-    assert lib.pflbm_workspace_bytes(C.byref(d16)) >= (42 * 2 + 8 + 1) * N
+    assert lib.pflbm_workspace_bytes(C.byref(d32)) >= (2 * 42 * 4 + 8) * N
+    assert lib.pflbm_workspace_bytes(C.byref(d16)) >= (2 * 42 * 2 + 8 + 1 + 4) * N
+    # the in-place AA scheme keeps one population buffer
+    a32 = L.Desc(32, 32, 32, 5, 1, 1, 0, 1)
+    assert (42 * 4 + 8) * N <= lib.pflbm_workspace_bytes(C.byref(a32)) < (2 * 42 * 4) * N
     for bad in (L.Desc(0, 4, 4, 0, 0, 0, 0), L.Desc(4, 4, 4, 9, 0, 0, 0),
-                L.Desc(4, 4, 4, 0, 3, 0, 0), L.Desc(4, 4, 4, 0, 0, 2, 0)):
+                L.Desc(4, 4, 4, 0, 3, 0, 0), L.Desc(4, 4, 4, 0, 0, 2, 0),
+                L.Desc(4, 4, 4, 0, 0, 0, 0, 2)):
         assert lib.pflbm_workspace_bytes(C.byref(bad)) == 0
     ctx = C.c_void_p()
     assert lib.pflbm_create(C.byref(L.Desc(0, 4, 4, 0, 0, 0, 0)), C.c_void_p(256), 1 << 20,
@@ -110,6 +114,71 @@ def test_xcd_remap_is_a_bijection_with_contiguous_ranges(nb):
         sel = np.sort(out[b % 8 == x])
         if len(sel):
             assert (np.diff(sel) == 1).all()
+
+
+def _pull_map(nx, ny, nz, periodic, solid, c):
+    """Slot (population, cell) each fluid cell pulls population i from, under
+    the two-buffer pull rule the kernels use: slot(i, y - c_i) if y - c_i is
+    fluid, else the bounce-back slot(opp i, y)."""
+    q = len(c)
+    opp = [0] + [i + 1 if i % 2 else i - 1 for i in range(1, q)]
+
+    def nb(x, y, z, d):
+        X, Y, Z = x + d[0], y + d[1], z + d[2]
+        for v, n, p in ((X, nx, periodic[0]), (Y, ny, periodic[1]), (Z, nz, periodic[2])):
+            if (v < 0 or v >= n) and not p:
+                return None
+        X, Y, Z = X % nx, Y % ny, Z % nz
+        idx = X + nx * (Y + ny * Z)
+        return None if solid[idx] else idx
+
+    reads = {}
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                idx = x + nx * (y + ny * z)
+                if solid[idx]:
+                    continue
+                for i in range(q):
+                    s = nb(x, y, z, -c[i]) if i else idx
+                    reads[(i, idx)] = (opp[i], idx) if s is None else (i, s)
+    return reads, opp
+
+
+@pytest.mark.parametrize("q", [15, 27])
+def test_pull_streaming_reads_each_slot_once_and_is_streaming(q):
+    """The pull rule reads every fluid slot of the previous state exactly once
+    (a permutation), and what cell y receives in direction i is what cell
+    y - c_i emitted in direction i, or its own emission in direction opp i
+    behind a wall or solid (halfway bounce-back)."""
+    from oracle import lattice as OL
+    c = (OL.D3Q15 if q == 15 else OL.D3Q27).c_np
+    # the library's order: rest, then opposite pairs adjacent
+    order = [0]
+    used = {0}
+    for i in range(1, q):
+        if i in used:
+            continue
+        j = [k for k in range(q) if (c[k] == -c[i]).all()][0]
+        order += [i, j]
+        used |= {i, j}
+    c = c[order]
+    rng = np.random.default_rng(0)
+    nx, ny, nz = 5, 4, 3
+    solid = rng.uniform(size=nx * ny * nz) < 0.15
+    fluid_slots = {(i, idx) for i in range(q) for idx in range(nx * ny * nz) if not solid[idx]}
+    for periodic in ((True, False, True), (False, False, False), (True, True, True)):
+        reads, opp = _pull_map(nx, ny, nz, periodic, solid, c)
+        src = list(reads.values())
+        assert len(set(src)) == len(src) == len(fluid_slots) and set(src) == fluid_slots
+        for (i, y), (j, x) in reads.items():
+            if j == i and x != y:
+                X = np.array([x % nx, (x // nx) % ny, x // (nx * ny)])
+                Y = np.array([y % nx, (y // nx) % ny, y // (nx * ny)])
+                d = (Y - X - c[i] + np.array([nx, ny, nz])) % np.array([nx, ny, nz])
+                assert (d == 0).all()
+            elif i:
+                assert j == opp[i] and x == y
 
 
 def _aa_maps(nx, ny, nz, periodic, solid, c, odd):

@@ -16,10 +16,11 @@ pytestmark = pytest.mark.gpu
 
 
 def _gpu_grads(wl, precision, collision, nsteps, K, depth, target, ckpt=None, M=None, sigma=None,
-               stats=None):
+               stats=None, streaming="ab"):
     from paper_2206_11637_amd.rollout import amplitude_rollout
     from paper_2206_11637_amd.sim import Simulation
-    sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, precision, collision, wl.solid, wl.params)
+    sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, precision, collision, wl.solid, wl.params,
+                     streaming=streaming)
     dev = sim.device
     phi0 = torch.tensor(wl.phi0, dtype=torch.float64, device=dev, requires_grad=True)
     Mt = torch.tensor(M if M is not None else wl.params.mobility, dtype=torch.float64, device=dev,
@@ -160,17 +161,34 @@ def test_config3_gradients_match_central_differences_fp64():
         assert abs(ad - fd) <= 1e-4 * abs(fd) + floor
 
 
+@pytest.mark.parametrize("streaming", ["ab", "aa"])
 @pytest.mark.parametrize("precision,tol", [("fp32", 0.25), ("fp16s", 1.0)])
-def test_reduced_precision_gradients_track_fp64(precision, tol):
+def test_reduced_precision_gradients_track_fp64(precision, tol, streaming):
     """FP32 arithmetic (FP32 or FP16 storage) forward + FP32 adjoint with FP64
     parameter-gradient sums, against the FP64 gradients (errors reported)."""
     wl = W.config3()
     N, K = 400, 10
-    say(f"case: config3 {precision} gradients vs fp64 over {N} steps")
+    say(f"case: config3 {precision} {streaming} gradients vs fp64 over {N} steps")
     target = _config3_target(wl, N, K)
     L64, dphi64, dM64, ds64, _ = _gpu_grads(wl, "fp64", "mrt", N, K, 64.0, target)
-    L, dphi, dM, ds, _ = _gpu_grads(wl, precision, "mrt", N, K, 64.0, target)
+    L, dphi, dM, ds, _ = _gpu_grads(wl, precision, "mrt", N, K, 64.0, target, streaming=streaming)
     e_phi = (dphi - dphi64).abs().max().item() / dphi64.abs().max().item()
     say(f"  {precision}: dM rel {_rel(dM, dM64):.2e} dsigma rel {_rel(ds, ds64):.2e} "
         f"dphi0 normwise {e_phi:.2e} L rel {_rel(L, L64):.2e}")
     assert _rel(dM, dM64) <= tol and _rel(ds, ds64) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_in_place_scheme_gives_the_same_gradients(precision, tol):
+    """The reverse mode over AA (in-place) saved states reads the same primal
+    values as over two-buffer states, so the gradients agree to rounding."""
+    wl = _small("mrt", True)
+    nsteps, K = 23, 1
+    target = np.random.default_rng(8).normal(0, 0.05, nsteps)
+    say(f"case: adjoint AA vs AB {precision}")
+    La, pa, Ma, sa, _ = _gpu_grads(wl, precision, "mrt", nsteps, K, 12.0, target, ckpt=4)
+    Lb, pb, Mb, sb, _ = _gpu_grads(wl, precision, "mrt", nsteps, K, 12.0, target, ckpt=4,
+                                   streaming="aa")
+    e_phi = (pa - pb).abs().max().item() / pa.abs().max().item()
+    say(f"  L {_rel(Lb, La):.1e} dM {_rel(Mb, Ma):.1e} dsigma {_rel(sb, sa):.1e} dphi0 {e_phi:.1e}")
+    assert _rel(Lb, La) <= tol and _rel(Mb, Ma) <= tol and _rel(sb, sa) <= tol and e_phi <= tol

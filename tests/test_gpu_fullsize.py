@@ -11,10 +11,10 @@ from gpu_util import perm_to_oracle, say, window_check
 pytestmark = pytest.mark.gpu
 
 
-def _sampled_check(wl, precision, warm, centres, tol_h, tol_g, collision="mrt"):
+def _sampled_check(wl, precision, warm, centres, tol_h, tol_g, collision="mrt", streaming="ab"):
     from paper_2206_11637_amd.sim import from_workload
-    say(f"case: {wl.name} {precision} warm {warm}")
-    sim = from_workload(wl, precision=precision, collision=collision)
+    say(f"case: {wl.name} {precision} {streaming} warm {warm}")
+    sim = from_workload(wl, precision=precision, collision=collision, streaming=streaming)
     r0 = sim.reduce()
     sim.step(warm)
     h_n, g_n = sim.populations()
@@ -34,6 +34,12 @@ def test_rising_bubble_fp32_full_size_windows():
     wl = W.config1()
     centres = [(64, 64, 64), (64 + 16, 64, 64), (3, 2, 100), (127, 511, 0), (40, 300, 90)]
     _sampled_check(wl, "fp32", 40, centres, 2e-5, 2e-5)
+
+
+def test_rising_bubble_fp32_in_place_full_size_windows():
+    wl = W.config1()
+    centres = [(64, 64, 64), (127, 0, 127), (20, 400, 30)]
+    _sampled_check(wl, "fp32", 41, centres, 2e-5, 2e-5, streaming="aa")
 
 
 def test_rising_bubble_fp64_full_size_windows():

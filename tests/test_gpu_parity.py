@@ -13,9 +13,12 @@ pytestmark = pytest.mark.gpu
 TOL64 = 1e-12   # normwise per field after N steps (FP64 path vs FP64 oracle)
 
 
-def _sim(wl, precision="fp64", collision="mrt"):
+STREAMING = ["ab", "aa"]
+
+
+def _sim(wl, precision="fp64", collision="mrt", streaming="ab"):
     from paper_2206_11637_amd.sim import from_workload
-    return from_workload(wl, precision=precision, collision=collision)
+    return from_workload(wl, precision=precision, collision=collision, streaming=streaming)
 
 
 def _compare_fields(sim, grid, prm, h, g, tol, label):
@@ -30,15 +33,16 @@ def _compare_fields(sim, grid, prm, h, g, tol, label):
     return errs
 
 
+@pytest.mark.parametrize("streaming", STREAMING)
 @pytest.mark.parametrize("collision", ["bgk", "mrt"])
-def test_capillary_wave_32cube_fp64_matches_oracle_after_200_steps(collision):
+def test_capillary_wave_32cube_fp64_matches_oracle_after_200_steps(collision, streaming):
     wl = W.config0()
-    say(f"case: capillary wave 32^3 fp64 {collision} 200 steps")
+    say(f"case: capillary wave 32^3 fp64 {collision} {streaming} 200 steps")
     grid, prm, h, g = oracle_setup(wl, collision)
     h, g = OP.run(grid, prm, h, g, wl.steps)
-    sim = _sim(wl, "fp64", collision)
+    sim = _sim(wl, "fp64", collision, streaming)
     sim.step(wl.steps)
-    _compare_fields(sim, grid, prm, h, g, TOL64, f"config0 {collision}")
+    _compare_fields(sim, grid, prm, h, g, TOL64, f"config0 {collision} {streaming}")
     r = sim.reduce()
     ro = OP.reductions(grid, h, g).numpy()
     assert abs(r[0] - ro[0]) <= 1e-12 * abs(ro[0])
@@ -56,15 +60,16 @@ RAGGED = [
 ]
 
 
+@pytest.mark.parametrize("streaming", STREAMING)
 @pytest.mark.parametrize("case", RAGGED, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}-p{''.join(str(int(v)) for v in c[3])}-s{c[4]}-n{c[5]}")
 @pytest.mark.parametrize("collision", ["bgk", "mrt"])
-def test_ragged_grids_walls_and_solids_match_oracle(case, collision):
+def test_ragged_grids_walls_and_solids_match_oracle(case, collision, streaming):
     nx, ny, nz, per, frac, steps = case
     wl = W.random_state(nx, ny, nz, periodic=per, solid_fraction=frac, seed=nx * 7 + ny,
                         steps=steps)
-    say(f"case: ragged {case} {collision}")
+    say(f"case: ragged {case} {collision} {streaming}")
     grid, prm, h, g = oracle_setup(wl, collision)
-    sim = _sim(wl, "fp64", collision)
+    sim = _sim(wl, "fp64", collision, streaming)
     _compare_fields(sim, grid, prm, h, g, TOL64, "init")
     h, g = OP.run(grid, prm, h, g, steps)
     sim.step(steps)
@@ -72,10 +77,11 @@ def test_ragged_grids_walls_and_solids_match_oracle(case, collision):
     _compare_fields(sim, grid, prm, h, g, TOL64, f"after {steps}")
 
 
-def test_zero_steps_and_resume_are_bitwise():
+@pytest.mark.parametrize("streaming", STREAMING)
+def test_zero_steps_and_resume_are_bitwise(streaming):
     wl = W.random_state(70, 21, 13, periodic=(True, False, True), solid_fraction=0.05, seed=4)
-    say("case: resume 70x21x13")
-    a = _sim(wl, "fp64")
+    say(f"case: resume 70x21x13 {streaming}")
+    a = _sim(wl, "fp64", streaming=streaming)
     h0, g0 = a.populations()
     a.step(0)
     h1, g1 = a.populations()
@@ -84,34 +90,35 @@ def test_zero_steps_and_resume_are_bitwise():
     buf = a.save_state()
     a.step(6)
     ha, ga = a.populations()
-    b = _sim(wl, "fp64")
+    b = _sim(wl, "fp64", streaming=streaming)
     b.load_state(buf, 5)
     b.step(6)
     hb, gb = b.populations()
     assert torch.equal(ha, hb) and torch.equal(ga, gb)
     # FP16 storage resumes bitwise too
-    c = _sim(wl, "fp16s")
+    c = _sim(wl, "fp16s", streaming=streaming)
     c.step(3)
     buf = c.save_state()
     c.step(4)
     hc, _ = c.populations()
-    d = _sim(wl, "fp16s")
+    d = _sim(wl, "fp16s", streaming=streaming)
     d.load_state(buf, 3)
     d.step(4)
     hd, _ = d.populations()
     assert torch.equal(hc, hd)
 
 
+@pytest.mark.parametrize("streaming", STREAMING)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_translation_invariance_is_bitwise(precision):
+def test_translation_invariance_is_bitwise(precision, streaming):
     wl = W.random_state(70, 12, 9, periodic=(True, True, True), seed=8)
-    say(f"case: translation {precision}")
+    say(f"case: translation {precision} {streaming}")
     sx, sy, sz = 5, 3, 2
     rolled = W.Workload(wl.name, wl.nx, wl.ny, wl.nz, wl.periodic, wl.params,
                         np.roll(wl.phi0, (sz, sy, sx), (0, 1, 2)),
                         np.roll(wl.u0, (sz, sy, sx), (1, 2, 3)),
                         np.roll(wl.pstar0, (sz, sy, sx), (0, 1, 2)), None, wl.steps)
-    a, b = _sim(wl, precision), _sim(rolled, precision)
+    a, b = _sim(wl, precision, streaming=streaming), _sim(rolled, precision, streaming=streaming)
     a.step(7)
     b.step(7)
     pa, _, _ = a.moments()
@@ -119,11 +126,12 @@ def test_translation_invariance_is_bitwise(precision):
     assert torch.equal(torch.roll(pa, (sz, sy, sx), (0, 1, 2)), pb)
 
 
-def test_mass_conserved_on_gpu_all_precisions():
+@pytest.mark.parametrize("streaming", STREAMING)
+def test_mass_conserved_on_gpu_all_precisions(streaming):
     wl = W.config4(scale=8)   # tube mask, walls
-    say("case: mass conservation taylor tube /8")
+    say(f"case: mass conservation taylor tube /8 {streaming}")
     for precision, tol in (("fp64", 1e-13), ("fp32", 2e-6), ("fp16s", 1e-3)):
-        sim = _sim(wl, precision)
+        sim = _sim(wl, precision, streaming=streaming)
         r0 = sim.reduce()
         sim.step(100)
         r1 = sim.reduce()
@@ -132,15 +140,16 @@ def test_mass_conserved_on_gpu_all_precisions():
         assert drift <= tol
 
 
+@pytest.mark.parametrize("streaming", STREAMING)
 @pytest.mark.parametrize("precision,tol_phi", [("fp32", 1e-4), ("fp16s", 5e-4)])
-def test_reduced_precision_forms_track_fp64(precision, tol_phi):
+def test_reduced_precision_forms_track_fp64(precision, tol_phi, streaming):
     """FP32 and FP16-storage forms against the FP64 path on the capillary
     wave (errors reported; bounds set from the rounding units)."""
     wl = W.config0()
-    say(f"case: config0 {precision} vs fp64")
+    say(f"case: config0 {precision} {streaming} vs fp64")
     ref = _sim(wl, "fp64")
     ref.step(wl.steps)
-    sim = _sim(wl, precision)
+    sim = _sim(wl, precision, streaming=streaming)
     sim.step(wl.steps)
     pr, ur, _ = ref.moments()
     p, u, _ = sim.moments()
@@ -176,24 +185,30 @@ def test_unstable_run_is_reported_not_silent():
 
 
 def _split_state(buf, N, precision):
-    """Saved-state bytes -> (h, g, phi, phi_prev) as integer views (bitwise
-    comparison); layout h[15][N], g[27][N], phi[N], phi_prev[N]."""
+    """Saved-state bytes -> (h, g, phi[, phi_prev]) as integer views (bitwise
+    comparison); layout h[15][N], g[27][N], phi^n[N] and, for FP16 storage,
+    phi^{n-1}[N]."""
     ss, rs = {"fp64": (8, 8), "fp32": (4, 4), "fp16s": (2, 4)}[precision]
     it = {2: torch.int16, 4: torch.int32, 8: torch.int64}
     o1, o2, o3 = 15 * N * ss, 42 * N * ss, 42 * N * ss + N * rs
-    return (buf[:o1].view(it[ss]).reshape(15, N), buf[o1:o2].view(it[ss]).reshape(27, N),
-            buf[o2:o3].view(it[rs]), buf[o3:o3 + N * rs].view(it[rs]))
+    parts = [buf[:o1].view(it[ss]).reshape(15, N), buf[o1:o2].view(it[ss]).reshape(27, N),
+             buf[o2:o3].view(it[rs])]
+    if precision == "fp16s":
+        parts.append(buf[o3:o3 + N * rs].view(it[rs]))
+    assert buf.numel() == o3 + (N * rs if precision == "fp16s" else 0)
+    return parts
 
 
+@pytest.mark.parametrize("streaming", STREAMING)
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16s"])
-def test_out_of_place_step_between_saved_states_is_bitwise(precision):
+def test_out_of_place_step_between_saved_states_is_bitwise(precision, streaming):
     """pflbm_step_states (used by checkpoint recompute) equals the in-place
-    step, for both parities, with walls and solids.  Solid cells' population
-    slots are never written by a step (nor read), so only fluid cells are
-    compared there."""
+    step over several steps, with walls and solids.  Solid cells' population
+    slots and FP16 shift references are never written by a step (nor read),
+    so only fluid cells are compared there."""
     wl = W.random_state(70, 21, 13, periodic=(True, False, True), solid_fraction=0.05, seed=9)
-    say(f"case: step_states {precision}")
-    sim = _sim(wl, precision)
+    say(f"case: step_states {precision} {streaming}")
+    sim = _sim(wl, precision, streaming=streaming)
     N = wl.nx * wl.ny * wl.nz
     fluid = torch.from_numpy(~np.asarray(wl.solid, dtype=bool).reshape(-1)).to(sim.device)
     assert 0 < int(fluid.sum()) < N
@@ -208,4 +223,24 @@ def test_out_of_place_step_between_saved_states_is_bitwise(precision):
         a, b = _split_state(nxt, N, precision), _split_state(ref, N, precision)
         assert torch.equal(a[0][:, fluid], b[0][:, fluid]), ("h", n)
         assert torch.equal(a[1][:, fluid], b[1][:, fluid]), ("g", n)
-        assert torch.equal(a[2], b[2]) and torch.equal(a[3], b[3]), ("phi", n)
+        assert torch.equal(a[2], b[2]), ("phi", n)
+        if precision == "fp16s":   # the shift reference is defined on fluid cells
+            assert torch.equal(a[3][fluid], b[3][fluid]), ("phi_prev", n)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_both_streaming_schemes_give_identical_results(precision):
+    """The two-buffer fused step and the in-place AA step do the same
+    arithmetic on the same values (phi summed in the same order), so their
+    moments and populations agree bitwise, for both parities, with walls and
+    solids."""
+    wl = W.random_state(70, 21, 13, periodic=(True, False, True), solid_fraction=0.05, seed=21)
+    say(f"case: AB vs AA {precision}")
+    a, b = _sim(wl, precision, streaming="ab"), _sim(wl, precision, streaming="aa")
+    for n in (5, 2):
+        a.step(n)
+        b.step(n)
+        for x, y in zip(a.moments(), b.moments()):
+            assert torch.equal(x, y)
+        for x, y in zip(a.populations(), b.populations()):
+            assert torch.equal(x, y)
