@@ -29,22 +29,26 @@ HBM_PEAK_GBPS = 8000.0
 # is one kernel (k_step), so this is also that kernel's figure.
 STEP_BYTES = {"fp64": 688, "fp32": 344, "fp16s": 176}
 CELL_KERNEL_BYTES = STEP_BYTES
+# the in-place AA scheme's collide-and-stream kernel alone: populations once
+# each way and phi read once (its separate phi pass writes phi)
+AA_CELL_KERNEL_BYTES = {"fp64": 680, "fp32": 340, "fp16s": 172}
 # HBM bytes per launch of k_step on the rising-bubble lattice from rocprofv3
 # FETCH_SIZE / WRITE_SIZE, scaled by the factors a plain 2 GiB device copy
-# gives on the same box (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE); None until
-# measured for the current kernel, and to be re-measured whenever it changes
-TRAFFIC = {"fp32": None, "fp16s": None, "fp64": None}
+# gives on the same box (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE); taken for
+# the current kernel (profiles/k_step_rising_bubble_128x512x128_hbm_traffic.txt)
+# and to be re-measured whenever it changes
+TRAFFIC = {"fp32": 3.296e9, "fp16s": 1.693e9, "fp64": 5.866e9}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_form(wl, precision, steps, warmup, collision="mrt"):
+def time_form(wl, precision, steps, warmup, collision="mrt", streaming="ab"):
     import torch
 
     from paper_2206_11637_amd.sim import from_workload
-    sim = from_workload(wl, precision=precision, collision=collision)
+    sim = from_workload(wl, precision=precision, collision=collision, streaming=streaming)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -58,7 +62,8 @@ def time_form(wl, precision, steps, warmup, collision="mrt"):
     cells = wl.cells
     mlups = cells * steps / (wall_ms * 1e-3) / 1e6
     cell_avg = cell_ms / steps
-    achieved = CELL_KERNEL_BYTES[precision] * cells / (cell_avg * 1e-3) / 1e9
+    kb = (AA_CELL_KERNEL_BYTES if streaming == "aa" else CELL_KERNEL_BYTES)[precision]
+    achieved = kb * cells / (cell_avg * 1e-3) / 1e9
     out = dict(mlups=mlups, ms_per_step=wall_ms / steps, cell_kernel_ms=cell_avg,
                phi_kernel_ms=phi_ms / steps, cell_kernel_GBps=achieved,
                cell_kernel_frac=achieved / HBM_PEAK_GBPS,
@@ -232,6 +237,9 @@ def main():
     if not args.no_forms:
         half = max(args.steps // 2, 10)
         form("fp64_rising_bubble_128x512x128", time_form, wl1, "fp64", half, args.warmup)
+        # the in-place AA scheme: half the population memory, a separate phi pass
+        form("fp32_in_place_aa_rising_bubble_128x512x128", time_form, wl1, "fp32", half, args.warmup,
+             "mrt", "aa")
         del wl1
         wl2 = W.config2()
         form("fp32_drop_impact_384^3", time_form, wl2, "fp32", half, args.warmup)
@@ -264,6 +272,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rising_bubble_128x512x128", "cells": 128 * 512 * 128,
                    "lattices": "D3Q15+D3Q27", "collision": "mrt", "storage": prec,
+                   "streaming": "two buffers, pull, phase field fused into the step",
                    "boundaries": "bounce-back on all faces"},
         "roofline": {"bound": "hbm", "achieved": round(main_form["cell_kernel_GBps"], 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
