@@ -64,11 +64,12 @@ typedef enum {
   PFLBM_FP64 = 0,        /* FP64 populations, FP64 arithmetic                     */
   PFLBM_FP32 = 1,        /* FP32 populations, FP32 arithmetic                     */
   PFLBM_FP32_FP16S = 2   /* FP32 arithmetic, populations stored as FP16 of
-                            (f_i - s_i) * 2^k; for h, s_i = w_i phi^n of one
-                            cell: with PFLBM_STREAM_AB the cell that reads the
-                            value next step, with PFLBM_STREAM_AA the cell that
-                            wrote it; for g, s_i = 0; k per lattice from
-                            fp16_scale_log2                                      */
+                            value * 2^k, k per lattice from fp16_scale_log2      */
+  /* Both FP32-arithmetic forms store h shifted: a slot holds h_i - w_i phi^n(r)
+     with r the cell that reads it in the next step, and the collision works on
+     deviations from w_i phi^{n-1} of the cell (rounding then acts on the
+     per-step change, not on h ~ w_i); g is stored unshifted.  FP64 stores plain
+     values. */
 } pflbm_precision;
 
 typedef enum { PFLBM_BGK = 0, PFLBM_MRT = 1 } pflbm_collision;
@@ -168,8 +169,8 @@ pflbm_status pflbm_read_populations(pflbm_ctx* ctx, double* d_h, double* d_g);
 pflbm_status pflbm_reduce(pflbm_ctx* ctx, double out_host[5]);
 
 /* Bytes of one saved state: h [15][N] and g [27][N] in storage precision
- * (layout of the streaming scheme), phi^n [N] and, for FP16S storage only,
- * phi^{n-1} [N] (the shift reference; defined on fluid cells). */
+ * (layout of the streaming scheme), phi^n [N] and, for the FP32 and FP16S
+ * forms, phi^{n-1} [N] (the shift reference; defined on fluid cells). */
 size_t pflbm_state_bytes(const pflbm_ctx* ctx);
 
 /* Copies the state to / from d_buf (device-to-device, asynchronous).  The

@@ -342,7 +342,7 @@ struct AdjArgs {
   const S* ph;
   const S* pg;
   const R* pphi;
-  const R* pphi_prev;   // phi^{n-1}: FP16 shift reference of the level-n populations
+  const R* pphi_prev;   // phi^{n-1}: shift reference of the level-n populations (shifted forms)
   const unsigned char* mask;
   // adjoint of level n+1 (natural layout) and of level n
   const R* lh_in;
@@ -378,9 +378,15 @@ void k_adj_cell(AdjArgs<S> a) {
     const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
     const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
     const Nbhd nb = make_nbhd(x, y, z, G);
-    R ref[Q_H], h[Q_H], g[Q_G];
-    shift_refs<S, RULE>(a.pphi_prev, idx, nb, walls, ref);
-    load_pops<S, RULE, false>(a.ph, a.pg, G.N, idx, nb, walls, a.cd, ref, h, g);
+    // primal populations of level n, absolute (h_i = h'_i + w_i phi_ref)
+    R h[Q_H], g[Q_G];
+    load_h<S, RULE, false>(a.ph, G.N, idx, nb, walls, a.cd.inv_scale_h, h);
+    load_g<S, RULE, false>(a.pg, G.N, idx, nb, walls, a.cd.inv_scale_g, g);
+    if (St::kShift) {
+      const R ref = a.pphi_prev[idx];
+#pragma unroll
+      for (int i = 0; i < Q_H; ++i) h[i] += R(wh(i)) * ref;
+    }
     R Gx, Gy, Gz, lap;
     stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
     // transposed streaming: Lambda of the slot each post-collision value went to

@@ -72,10 +72,21 @@ __device__ __forceinline__ void pair_moments(const R (&f)[Q], R& mx, R& my, R& m
   }
 }
 
+// Shifted representation of the phase-field populations.  The collision
+// works on deviations h'_i = h_i - w_i phi_ref from a per-cell reference
+// (the cell's phase field one step earlier; zero for the FP64 form), so the
+// rounding of every step acts on quantities of the size of the change instead
+// of on h ~ w_i.  phi = phi_ref + sum_i h'_i.
+template <typename R>
+__device__ __forceinline__ R phi_of(const R (&hd)[Q_H], R phi_ref) {
+  return phi_ref + sum_h(hd);
+}
+
 // Cell state after the force prologue (everything the collisions need).
 template <typename R>
 struct CellState {
-  R phi, rho, omega, theta, nx, ny, nz;
+  R phi, dphi;       // phi and phi - phi_ref
+  R rho, omega, theta, nx, ny, nz;
   R p, jx, jy, jz;
   R ux, uy, uz;      // force-corrected velocity u = j + F/(2 rho)
   R Fx, Fy, Fz;      // total force
@@ -83,11 +94,12 @@ struct CellState {
 };
 
 // S1-S11: moments, chemical potential, forces and velocity of one cell.
+// phi = phi_ref + dphi with dphi = sum of the h deviations (S1).
 template <typename R>
-__device__ __forceinline__ void prologue(const R (&h)[Q_H], const R (&g)[Q_G], R Gx, R Gy,
-                                         R Gz, R lap, const Phys<R>& P, CellState<R>& c) {
-  const R phi = sum_h(h);
+__device__ __forceinline__ void prologue(R phi, R dphi, const R (&g)[Q_G], R Gx, R Gy, R Gz,
+                                         R lap, const Phys<R>& P, CellState<R>& c) {
   c.phi = phi;
+  c.dphi = dphi;
   c.rho = P.rho_L + phi * P.drho;
   c.omega = R(1) / (P.tau_L + phi * P.dtau);
   c.theta = P.theta_k * phi * (R(1) - phi);
@@ -198,8 +210,10 @@ __device__ __forceinline__ void collide_g(R (&g)[Q_G], const CellState<R>& c, co
   }
 }
 
-// S14-S15: phase-field collision in place (needs u from the hydro prologue),
-// in the same pair form.
+// S14-S15: phase-field collision in place on the deviations h' (needs u
+// from the hydro prologue), in the same pair form.  With the reference
+// subtracted, h^eq_i - w_i phi_ref = w_i [dphi + phi (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)]
+// and the second moment of h' is that of h minus phi_ref I/3.
 template <typename R, bool MRT>
 __device__ __forceinline__ void collide_h(R (&h)[Q_H], const CellState<R>& c, const Phys<R>& P) {
   const R uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
@@ -214,16 +228,16 @@ __device__ __forceinline__ void collide_h(R (&h)[Q_H], const CellState<R>& c, co
     R jx, jy, jz;
     Sym<R> Pi;
     pair_moments<R, false, Q_H>(h, jx, jy, jz, Pi);
-    // moments of h^eq: phi u, phi (I/3 + u u)
+    // moments of h^eq - w phi_ref: phi u, dphi I/3 + phi u u
     a1x = phi * c.ux - jx;
     a1y = phi * c.uy - jy;
     a1z = phi * c.uz - jz;
-    const R p3 = phi * (R(1) / R(3));
+    const R p3 = c.dphi * (R(1) / R(3));
     A2 = Sym<R>{p3 + phi * c.ux * c.ux - Pi.xx, p3 + phi * c.uy * c.uy - Pi.yy,
                 p3 + phi * c.uz * c.uz - Pi.zz, phi * c.ux * c.uy - Pi.xy,
                 phi * c.ux * c.uz - Pi.xz, phi * c.uy * c.uz - Pi.yz};
   }
-  const R base = phi * (R(1) - R(1.5) * uu);
+  const R base = c.dphi - R(1.5) * phi * uu;
   {
     const R w = R(wh(0));
     R v = h[0] + shi * (w * base - h[0]);

@@ -41,6 +41,17 @@
 // with phi^n staged from the stored field (tile + halo, 3 planes, in LDS),
 // and a light pass (k_light, gather) then forms phi^{n+1}.
 //
+// Shifted storage (FP32 and FP16 forms): a slot holds h_i - w_i phi^n(r),
+// where r is the cell that reads it in the next step (x + c_i, or x itself
+// behind a wall; the writer knows phi^n(r) from its stencil planes), so the
+// reader finds its reference at its own index of the previous phi buffer and
+// works on deviations from w_i phi^{n-1}(self) without adding anything (see
+// phi_of in cell.hpp).  Values of the size of the per-step change are stored
+// and rounded instead of h ~ w_i; with plain FP32 storage the heavy phase
+// loses updates below its rounding unit while the light phase keeps them,
+// which made the FP32 phase mass drift by ~5e-9 per step in slow runs.  g is
+// stored unshifted (small in the p* gauge), and so is everything in FP64.
+//
 // Blocks are issued round-robin over the 8 XCDs; xcd_remap() renumbers them
 // so that each XCD walks one contiguous range of tiles, keeping the ring and
 // neighbour-population reuse inside one XCD's L2.
@@ -64,13 +75,9 @@ struct Geom {
 };
 
 // ---- storage codecs -------------------------------------------------------
-// ld/st take the shift s and the scale: stored = (f - s) * 2^k.  FP64 and
-// FP32 store f itself.  FP16 storage shifts every h population by w_i times a
-// phase field one step old, so both pure phases store values near zero; g is
-// stored unshifted (it is small in the p* gauge).  Two buffers: the phase
-// field phi^n of the cell that will read the value in step n + 1 (the reader
-// finds it at its own index of the previous phi buffer).  AA: phi^n of the
-// cell that wrote it (x - c_i, or x itself behind a wall, in both parities).
+// ld/st convert between the stored value and the compute type; FP16 storage
+// also scales by 2^k (stored = value * 2^k).  kShift: h is stored shifted
+// (see the header).
 template <typename S>
 struct Store;
 template <bool NT, typename T>
@@ -86,30 +93,30 @@ struct Store<double> {
   using R = double;
   static constexpr bool kShift = false;
   template <bool NT = true>
-  __device__ static R ld(const double* p, R, R) { return ld_nt<NT>(p); }
+  __device__ static R ld(const double* p, R) { return ld_nt<NT>(p); }
   template <bool NT = true>
-  __device__ static void st(double* p, R v, R, R) { st_nt<NT>(p, v); }
+  __device__ static void st(double* p, R v, R) { st_nt<NT>(p, v); }
 };
 template <>
 struct Store<float> {
   using R = float;
-  static constexpr bool kShift = false;
+  static constexpr bool kShift = true;
   template <bool NT = true>
-  __device__ static R ld(const float* p, R, R) { return ld_nt<NT>(p); }
+  __device__ static R ld(const float* p, R) { return ld_nt<NT>(p); }
   template <bool NT = true>
-  __device__ static void st(float* p, R v, R, R) { st_nt<NT>(p, v); }
+  __device__ static void st(float* p, R v, R) { st_nt<NT>(p, v); }
 };
 template <>
 struct Store<_Float16> {
   using R = float;
   static constexpr bool kShift = true;
   template <bool NT = true>
-  __device__ static R ld(const _Float16* p, R shift, R inv_scale) {
-    return static_cast<float>(ld_nt<NT>(p)) * inv_scale + shift;
+  __device__ static R ld(const _Float16* p, R inv_scale) {
+    return static_cast<float>(ld_nt<NT>(p)) * inv_scale;
   }
   template <bool NT = true>
-  __device__ static void st(_Float16* p, R v, R shift, R scale) {
-    st_nt<NT>(p, static_cast<_Float16>((v - shift) * scale));
+  __device__ static void st(_Float16* p, R v, R scale) {
+    st_nt<NT>(p, static_cast<_Float16>(v * scale));
   }
 };
 
@@ -353,57 +360,6 @@ __device__ __forceinline__ unsigned pull_off(int i, unsigned idx, const Nbhd& nb
                                                    : pair_off<S>(i, nb.at(-d.x, -d.y, -d.z), NS);
 }
 
-// Pre-collision h of one cell.  phi_prev: the cell's own phase field one step
-// earlier (the FP16 shift reference).
-template <typename S, bool NT>
-__device__ __forceinline__ void pull_h(const S* __restrict__ H, long long N, unsigned idx,
-                                       const Nbhd& nb, unsigned walls,
-                                       typename Store<S>::R phi_prev,
-                                       typename Store<S>::R inv_scale,
-                                       typename Store<S>::R (&h)[Q_H]) {
-  using St = Store<S>;
-  using R = typename St::R;
-  const unsigned NS = (unsigned)(N * (long long)sizeof(S));
-#pragma unroll
-  for (int i = 0; i < Q_H; ++i) {
-    const S* p = reinterpret_cast<const S*>(pair_base(H, N, i) + pull_off<S, false>(i, idx, nb, walls, NS));
-    h[i] = St::template ld<NT>(p, St::kShift ? R(wh(i)) * phi_prev : R(0), inv_scale);
-  }
-}
-
-template <typename S, bool NT>
-__device__ __forceinline__ void pull_g(const S* __restrict__ Gp, long long N, unsigned idx,
-                                       const Nbhd& nb, unsigned walls,
-                                       typename Store<S>::R inv_scale,
-                                       typename Store<S>::R (&g)[Q_G]) {
-  using St = Store<S>;
-  using R = typename St::R;
-  const unsigned NS = (unsigned)(N * (long long)sizeof(S));
-#pragma unroll
-  for (int i = 0; i < Q_G; ++i) {
-    const S* p = reinterpret_cast<const S*>(pair_base(Gp, N, i) + pull_off<S, true>(i, idx, nb, walls, NS));
-    g[i] = St::template ld<NT>(p, R(0), inv_scale);
-  }
-}
-
-// Post-collision values into the cell's own slots.  phr[i]: the phase field
-// phi^n of the cell that pulls slot (i, x) next step (x + c_i, or x itself
-// behind a wall); only FP16 storage uses it.
-template <typename S, bool NT>
-__device__ __forceinline__ void store_own(S* __restrict__ H, S* __restrict__ Gp, long long N,
-                                          unsigned idx, const Codec<typename Store<S>::R>& cd,
-                                          const typename Store<S>::R (&phr)[Q_H],
-                                          const typename Store<S>::R (&h)[Q_H],
-                                          const typename Store<S>::R (&g)[Q_G]) {
-  using St = Store<S>;
-  using R = typename St::R;
-#pragma unroll
-  for (int i = 0; i < Q_H; ++i)
-    St::template st<NT>(slot(H, N, i, idx), h[i], St::kShift ? R(wh(i)) * phr[i] : R(0), cd.scale_h);
-#pragma unroll
-  for (int i = 0; i < Q_G; ++i) St::template st<NT>(slot(Gp, N, i, idx), g[i], R(0), cd.scale_g);
-}
-
 // ---- read rules of a state ---------------------------------------------------
 // RULE_AB: two-buffer pull; RULE_AA_EVEN / RULE_AA_ODD: the AA parity of the
 // next step (a state after n steps is read with the rule of parity n).
@@ -420,95 +376,95 @@ __device__ __forceinline__ unsigned read_off(int i, unsigned idx, const Nbhd& nb
                                                    : pair_off<S>(opp(i), nb.at(-d.x, -d.y, -d.z), NS);
 }
 
-// Pre-collision populations of one cell under a read rule.  ref[i]: the FP16
-// shift reference of population i (only used by FP16 storage).
-template <typename S, int RULE, bool NT>
-__device__ __forceinline__ void load_pops(const S* __restrict__ H, const S* __restrict__ Gp,
-                                          long long N, unsigned idx, const Nbhd& nb,
-                                          unsigned walls, const Codec<typename Store<S>::R>& cd,
-                                          const typename Store<S>::R (&ref)[Q_H],
-                                          typename Store<S>::R (&h)[Q_H],
-                                          typename Store<S>::R (&g)[Q_G]) {
-  using St = Store<S>;
-  using R = typename St::R;
-  const unsigned NS = (unsigned)(N * (long long)sizeof(S));
-#pragma unroll
-  for (int i = 0; i < Q_H; ++i) {
-    const S* p = reinterpret_cast<const S*>(pair_base(H, N, i) + read_off<S, false, RULE>(i, idx, nb, walls, NS));
-    h[i] = St::template ld<NT>(p, St::kShift ? R(wh(i)) * ref[i] : R(0), cd.inv_scale_h);
-  }
-#pragma unroll
-  for (int i = 0; i < Q_G; ++i) {
-    const S* p = reinterpret_cast<const S*>(pair_base(Gp, N, i) + read_off<S, true, RULE>(i, idx, nb, walls, NS));
-    g[i] = St::template ld<NT>(p, R(0), cd.inv_scale_g);
-  }
-}
-
+// Pre-collision h of one cell as read (deviations from w_i phi^{n-1}(self)
+// for the shifted forms, plain values in FP64).
 template <typename S, int RULE, bool NT>
 __device__ __forceinline__ void load_h(const S* __restrict__ H, long long N, unsigned idx,
                                        const Nbhd& nb, unsigned walls,
-                                       const Codec<typename Store<S>::R>& cd,
-                                       const typename Store<S>::R (&ref)[Q_H],
+                                       typename Store<S>::R inv_scale,
                                        typename Store<S>::R (&h)[Q_H]) {
   using St = Store<S>;
-  using R = typename St::R;
   const unsigned NS = (unsigned)(N * (long long)sizeof(S));
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
     const S* p = reinterpret_cast<const S*>(pair_base(H, N, i) + read_off<S, false, RULE>(i, idx, nb, walls, NS));
-    h[i] = St::template ld<NT>(p, St::kShift ? R(wh(i)) * ref[i] : R(0), cd.inv_scale_h);
+    h[i] = St::template ld<NT>(p, inv_scale);
   }
 }
 
-// FP16 shift references of the populations a cell reads, from a phi^{n-1}
-// buffer: two buffers, the cell's own value; AA, the writer's (x - c_i, or x
-// behind a wall).  Zero when unused.
-template <typename S, int RULE>
-__device__ __forceinline__ void shift_refs(const typename Store<S>::R* __restrict__ phi_prev,
-                                           unsigned idx, const Nbhd& nb, unsigned walls,
-                                           typename Store<S>::R (&ref)[Q_H]) {
+template <typename S, int RULE, bool NT>
+__device__ __forceinline__ void load_g(const S* __restrict__ Gp, long long N, unsigned idx,
+                                       const Nbhd& nb, unsigned walls,
+                                       typename Store<S>::R inv_scale,
+                                       typename Store<S>::R (&g)[Q_G]) {
+  using St = Store<S>;
+  const unsigned NS = (unsigned)(N * (long long)sizeof(S));
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    const S* p = reinterpret_cast<const S*>(pair_base(Gp, N, i) + read_off<S, true, RULE>(i, idx, nb, walls, NS));
+    g[i] = St::template ld<NT>(p, inv_scale);
+  }
+}
+
+// phi^{n-1}(self), the reference of the shifted forms (0 in FP64)
+template <typename S>
+__device__ __forceinline__ typename Store<S>::R phi_ref_of(const typename Store<S>::R* __restrict__ phi_prev,
+                                                          unsigned idx) {
   using R = typename Store<S>::R;
-  if (!Store<S>::kShift) {
-#pragma unroll
-    for (int i = 0; i < Q_H; ++i) ref[i] = R(0);
-    return;
-  }
-  const R self = phi_prev[idx];
-#pragma unroll
-  for (int i = 0; i < Q_H; ++i) {
-    if (RULE == RULE_AB || i == 0) {
-      ref[i] = self;
-    } else {
-      const Dir d = ch(i);
-      ref[i] = (walls & (1u << nb27(-d.x, -d.y, -d.z))) ? self : phi_prev[nb.at(-d.x, -d.y, -d.z)];
-    }
-  }
+  return Store<S>::kShift ? phi_prev[idx] : R(0);
 }
 
-// AA writer references from an LDS tile (3 planes + halo) of phi^{n-1}
+// phi^n of the reader of each outgoing population (x + c_i, or x behind a
+// wall or solid), from three stencil planes; only the shifted forms use it.
 template <typename R>
-__device__ __forceinline__ void writer_refs_tile(const R* tp, int TX, int TY, int lx, int ly,
-                                                 unsigned walls, R (&ref)[Q_H]) {
-  const R self = tp[(TY + ly + 1) * TX + lx + 1];
+__device__ __forceinline__ void reader_phis(const R* pm, const R* p0, const R* pp, int TX, int lx,
+                                            int ly, R (&phr)[Q_H]) {
+  const R self = p0[(ly + 1) * TX + lx + 1];
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
     const Dir d = ch(i);
-    ref[i] = (i == 0 || (walls & (1u << nb27(-d.x, -d.y, -d.z))))
-                 ? self
-                 : tp[((1 - d.z) * TY + (ly + 1 - d.y)) * TX + (lx + 1 - d.x)];
+    const R* pl = d.z < 0 ? pm : (d.z > 0 ? pp : p0);
+    const R v = pl[(ly + 1 + d.y) * TX + (lx + 1 + d.x)];
+    phr[i] = (i == 0 || v == sentinel<R>()) ? self : v;
   }
 }
 
-// AA store of post-collision values; phi_self: the writer's phi^n (FP16 shift)
+// Post-collision value of population i for storage: the deviation h*'_i is
+// relative to w_i phi_ref; the slot must be relative to w_i phi^n(reader).
+template <typename S>
+__device__ __forceinline__ typename Store<S>::R rebase(int i, typename Store<S>::R v,
+                                                       typename Store<S>::R phi_ref,
+                                                       const typename Store<S>::R (&phr)[Q_H]) {
+  using R = typename Store<S>::R;
+  return Store<S>::kShift ? v + R(wh(i)) * (phi_ref - phr[i]) : v;
+}
+
+// Two buffers: post-collision values into the cell's own slots.
+template <typename S, bool NT>
+__device__ __forceinline__ void store_own(S* __restrict__ H, S* __restrict__ Gp, long long N,
+                                          unsigned idx, const Codec<typename Store<S>::R>& cd,
+                                          typename Store<S>::R phi_ref,
+                                          const typename Store<S>::R (&phr)[Q_H],
+                                          const typename Store<S>::R (&h)[Q_H],
+                                          const typename Store<S>::R (&g)[Q_G]) {
+  using St = Store<S>;
+#pragma unroll
+  for (int i = 0; i < Q_H; ++i)
+    St::template st<NT>(slot(H, N, i, idx), rebase<S>(i, h[i], phi_ref, phr), cd.scale_h);
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) St::template st<NT>(slot(Gp, N, i, idx), g[i], cd.scale_g);
+}
+
+// AA: post-collision values into the slots of the parity's write rule.
 template <typename S, bool ODD, bool NT>
 __device__ __forceinline__ void store_aa(S* __restrict__ H, S* __restrict__ Gp, long long N,
                                          unsigned idx, const Nbhd& nb, unsigned walls,
                                          const Codec<typename Store<S>::R>& cd,
-                                         typename Store<S>::R phi_self,
+                                         typename Store<S>::R phi_ref,
+                                         const typename Store<S>::R (&phr)[Q_H],
                                          const typename Store<S>::R (&h)[Q_H],
                                          const typename Store<S>::R (&g)[Q_G]) {
   using St = Store<S>;
-  using R = typename St::R;
   const unsigned NS = (unsigned)(N * (long long)sizeof(S));
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
@@ -518,7 +474,7 @@ __device__ __forceinline__ void store_aa(S* __restrict__ H, S* __restrict__ Gp, 
       if (!(walls & (1u << nb27(d.x, d.y, d.z)))) off = pair_off<S>(i, nb.at(d.x, d.y, d.z), NS);
     }
     S* p = reinterpret_cast<S*>(pair_base(H, N, i) + off);
-    St::template st<NT>(p, h[i], St::kShift ? R(wh(i)) * phi_self : R(0), cd.scale_h);
+    St::template st<NT>(p, rebase<S>(i, h[i], phi_ref, phr), cd.scale_h);
   }
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) {
@@ -528,7 +484,7 @@ __device__ __forceinline__ void store_aa(S* __restrict__ H, S* __restrict__ Gp, 
       if (!(walls & (1u << nb27(d.x, d.y, d.z)))) off = pair_off<S>(i, nb.at(d.x, d.y, d.z), NS);
     }
     S* p = reinterpret_cast<S*>(pair_base(Gp, N, i) + off);
-    St::template st<NT>(p, g[i], R(0), cd.scale_g);
+    St::template st<NT>(p, g[i], cd.scale_g);
   }
 }
 
@@ -547,8 +503,8 @@ struct StepArgs {
   const S* g_in;
   S* h_out;                  // state n + 1
   S* g_out;
-  const R* phi_prev;         // phi^{n-1} (FP16 storage: shift reference of state n)
-  R* phi_out;                // phi^n, written for FP16 storage (null otherwise)
+  const R* phi_prev;         // phi^{n-1}: shift reference of state n (shifted forms)
+  R* phi_out;                // phi^n, the reference of state n + 1 (shifted forms)
   const unsigned* nbr;       // solid-neighbour bits (mask only)
   Geom geo;
   Phys<R> P;
@@ -594,8 +550,10 @@ void k_step(StepArgs<S> a) {
   }
   const unsigned sxy = (unsigned)G.nx * (unsigned)G.ny;
 
-  // phi^n of plane p (own position kept: pulled h, walls, solid flag)
+  // phi^n of plane p (own position kept: pulled h, its reference, walls,
+  // solid flag)
   R hn[Q_H];
+  R refn = R(0);
   unsigned wn = 0;
   bool sn = true;
   auto plane = [&](int p) {
@@ -609,9 +567,9 @@ void k_step(StepArgs<S> a) {
       bool sol;
       wn = cell_walls<MASK>(ox, oy, pz, idx, G, a.nbr, sol);
       if (!sol) {
-        const R pp = St::kShift ? a.phi_prev[idx] : R(0);
-        pull_h<S, kNtPull>(a.h_in, G.N, idx, make_nbhd(ox, oy, pz, G), wn, pp, a.cd.inv_scale_h, hn);
-        v = sum_h(hn);
+        refn = phi_ref_of<S>(a.phi_prev, idx);
+        load_h<S, RULE_AB, kNtPull>(a.h_in, G.N, idx, make_nbhd(ox, oy, pz, G), wn, a.cd.inv_scale_h, hn);
+        v = phi_of(hn, refn);
         sn = false;
       }
     }
@@ -623,10 +581,9 @@ void k_step(StepArgs<S> a) {
         bool sol;
         const unsigned w = cell_walls<MASK>(hx, hy, pz, idx, G, a.nbr, sol);
         if (!sol) {
-          const R pp = St::kShift ? a.phi_prev[idx] : R(0);
           R hh[Q_H];
-          pull_h<S, false>(a.h_in, G.N, idx, make_nbhd(hx, hy, pz, G), w, pp, a.cd.inv_scale_h, hh);
-          hv = sum_h(hh);
+          load_h<S, RULE_AB, false>(a.h_in, G.N, idx, make_nbhd(hx, hy, pz, G), w, a.cd.inv_scale_h, hh);
+          hv = phi_of(hh, phi_ref_of<S>(a.phi_prev, idx));
         }
       }
       rp[hpos] = hv;
@@ -639,12 +596,13 @@ void k_step(StepArgs<S> a) {
     R h[Q_H];
 #pragma unroll
     for (int i = 0; i < Q_H; ++i) h[i] = hn[i];
+    const R ref = refn;
     const unsigned walls = wn;
     const bool work = active && !sn;
     const unsigned idx = x + G.nx * y + sxy * z;
     const Nbhd nb = make_nbhd(x, y, z, G);
     R g[Q_G];
-    if (work) pull_g<S, kNtPull>(a.g_in, G.N, idx, nb, walls, a.cd.inv_scale_g, g);
+    if (work) load_g<S, RULE_AB, kNtPull>(a.g_in, G.N, idx, nb, walls, a.cd.inv_scale_g, g);
     plane(z + 1);
     __syncthreads();
     if (work) {
@@ -653,23 +611,20 @@ void k_step(StepArgs<S> a) {
       const R* pp = ring + ((z + 1) & 3) * TXY;
       R Gx, Gy, Gz, lap;
       stencil3(pm, p0, pp, TX, lx, ly, Gx, Gy, Gz, lap);
+      // phi as the ring holds it (ref + sum h'); dphi = sum h' itself, so the
+      // equilibrium's zeroth moment matches the populations' without phi's
+      // rounding
+      const R phi = p0[opos];
       CellState<R> c;
-      prologue(h, g, Gx, Gy, Gz, lap, a.P, c);
+      prologue(phi, sum_h(h), g, Gx, Gy, Gz, lap, a.P, c);
       collide_g<R, MRT>(g, c, a.P);
       collide_h<R, MRT>(h, c, a.P);
       R phr[Q_H];
       if (St::kShift) {
-        const R self = p0[opos];
-#pragma unroll
-        for (int i = 0; i < Q_H; ++i) {
-          const Dir d = ch(i);
-          const R* pl = d.z < 0 ? pm : (d.z > 0 ? pp : p0);
-          const R v = pl[(ly + 1 + d.y) * TX + (lx + 1 + d.x)];
-          phr[i] = (i == 0 || v == sentinel<R>()) ? self : v;
-        }
-        a.phi_out[idx] = self;
+        reader_phis(pm, p0, pp, TX, lx, ly, phr);
+        a.phi_out[idx] = phi;
       }
-      store_own<S, kNtStore>(a.h_out, a.g_out, G.N, idx, a.cd, phr, h, g);
+      store_own<S, kNtStore>(a.h_out, a.g_out, G.N, idx, a.cd, ref, phr, h, g);
     }
   }
 }
@@ -682,7 +637,7 @@ struct CellArgs {
   S* h;                      // populations written (AA step; == h_in in place)
   S* g;
   const R* phi;              // phi^n (stencil source)
-  const R* phi_prev;         // phi^{n-1} (FP16 shift references)
+  const R* phi_prev;         // phi^{n-1}: shift reference of the state read
   const unsigned char* mask;
   Geom geo;
   Phys<R> P;
@@ -702,41 +657,45 @@ template <bool ODD> struct AaPolicy {
 };
 
 // In-place AA collide-and-stream of both lattices for one plane of one tile
-// (phi^n and, for FP16 storage, phi^{n-1} staged in LDS).  Also runs out of
-// place (h_in != h) between saved states.
+// (phi^n staged in LDS).  Also runs out of place (h_in != h) between saved
+// states.
 template <typename S, bool MRT, bool ODD, bool MASK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<S>::value)))
 void k_cell_aa(CellArgs<S> a) {
-  using R = typename Store<S>::R;
+  using St = Store<S>;
+  using R = typename St::R;
   extern __shared__ unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   const Geom& G = a.geo;
   const int TX = G.bx + 2, TY = G.by + 2;
-  R* tile_prev = tile + TX * TY * 3;          // only with FP16 storage
   const TileCoord t = tile_of_block(G);
   load_phi_tile<R, MASK>(tile, a.phi, a.mask, G, t);
-  if (Store<S>::kShift) load_phi_tile<R, MASK>(tile_prev, a.phi_prev, a.mask, G, t);
   __syncthreads();
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
   if (x >= G.nx || y >= G.ny) return;
   const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
-  const R self = tile[(TY + ly + 1) * TX + lx + 1];
-  if (self == sentinel<R>()) return;   // solid cell
+  const R* pm = tile;
+  const R* p0 = tile + TX * TY;
+  const R* pp = tile + 2 * TX * TY;
+  const R phi = p0[(ly + 1) * TX + lx + 1];
+  if (phi == sentinel<R>()) return;   // solid cell
   const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
   const Nbhd nb = make_nbhd(x, y, z, G);
-  R ref[Q_H];
-  if (Store<S>::kShift) writer_refs_tile(tile_prev, TX, TY, lx, ly, walls, ref);
   R h[Q_H], g[Q_G];
-  load_pops<S, ODD ? RULE_AA_ODD : RULE_AA_EVEN, AaPolicy<ODD>::nt_load>(a.h_in, a.g_in, G.N, idx, nb, walls,
-                                                                        a.cd, ref, h, g);
+  constexpr int RULE = ODD ? RULE_AA_ODD : RULE_AA_EVEN;
+  load_h<S, RULE, AaPolicy<ODD>::nt_load>(a.h_in, G.N, idx, nb, walls, a.cd.inv_scale_h, h);
+  load_g<S, RULE, AaPolicy<ODD>::nt_load>(a.g_in, G.N, idx, nb, walls, a.cd.inv_scale_g, g);
+  const R ref = phi_ref_of<S>(a.phi_prev, idx);
   R Gx, Gy, Gz, lap;
-  stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
+  stencil3(pm, p0, pp, TX, lx, ly, Gx, Gy, Gz, lap);
   CellState<R> c;
-  prologue(h, g, Gx, Gy, Gz, lap, a.P, c);
+  prologue(phi, sum_h(h), g, Gx, Gy, Gz, lap, a.P, c);
   collide_g<R, MRT>(g, c, a.P);
   collide_h<R, MRT>(h, c, a.P);
-  store_aa<S, ODD, AaPolicy<ODD>::nt_store>(a.h, a.g, G.N, idx, nb, walls, a.cd, self, h, g);
+  R phr[Q_H];
+  if (St::kShift) reader_phis(pm, p0, pp, TX, lx, ly, phr);
+  store_aa<S, ODD, AaPolicy<ODD>::nt_store>(a.h, a.g, G.N, idx, nb, walls, a.cd, ref, phr, h, g);
 }
 
 // Cell moments phi, u, p* of the current state with the step's force
@@ -755,7 +714,8 @@ __global__ __launch_bounds__(256) void k_moments(CellArgs<S> a) {
   const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
   if (x >= G.nx || y >= G.ny) return;
   const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
-  if (tile[(TY + ly + 1) * TX + lx + 1] == sentinel<R>()) {   // solid cell
+  const R phi = tile[(TY + ly + 1) * TX + lx + 1];
+  if (phi == sentinel<R>()) {   // solid cell
     if (a.out_phi) a.out_phi[idx] = 0.0;
     if (a.out_p) a.out_p[idx] = 0.0;
     if (a.out_u) { a.out_u[idx] = 0.0; a.out_u[G.N + idx] = 0.0; a.out_u[2 * G.N + idx] = 0.0; }
@@ -763,13 +723,12 @@ __global__ __launch_bounds__(256) void k_moments(CellArgs<S> a) {
   }
   const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
   const Nbhd nb = make_nbhd(x, y, z, G);
-  R ref[Q_H], h[Q_H], g[Q_G];
-  shift_refs<S, RULE>(a.phi_prev, idx, nb, walls, ref);
-  load_pops<S, RULE, false>(a.h_in, a.g_in, G.N, idx, nb, walls, a.cd, ref, h, g);
+  R g[Q_G];
+  load_g<S, RULE, false>(a.g_in, G.N, idx, nb, walls, a.cd.inv_scale_g, g);
   R Gx, Gy, Gz, lap;
   stencil(tile, TX, TY, lx, ly, Gx, Gy, Gz, lap);
   CellState<R> c;
-  prologue(h, g, Gx, Gy, Gz, lap, a.P, c);
+  prologue(phi, phi, g, Gx, Gy, Gz, lap, a.P, c);
   if (a.out_phi) a.out_phi[idx] = double(c.phi);
   if (a.out_p) a.out_p[idx] = double(c.p);
   if (a.out_u) {
@@ -785,7 +744,7 @@ struct LightArgs {
   const S* h;
   const S* g;
   const unsigned* nbr;
-  const R* phi_prev;   // phi^{n-1} of the state read (FP16 shift references)
+  const R* phi_prev;   // phi^{n-1}: shift reference of the state read
   Geom geo;
   Codec<R> cd;
   R* phi_out;          // gather target (compute precision)
@@ -796,8 +755,8 @@ struct LightArgs {
 
 enum LightMode { LM_GATHER = 0, LM_READ_POPS = 1, LM_REDUCE = 2 };
 
-// phi = sum of the h populations the next step reads (the state's phase
-// field), population readout, or per-block FP64 sums.
+// phi of the state (phi_ref + sum of the h deviations the next step reads,
+// in the order the step uses), population readout, or per-block FP64 sums.
 template <typename S, int RULE, bool MASK, int LM>
 __global__ __launch_bounds__(256) void k_light(LightArgs<S> a) {
   using R = typename Store<S>::R;
@@ -818,20 +777,21 @@ __global__ __launch_bounds__(256) void k_light(LightArgs<S> a) {
       }
     } else {
       const Nbhd nb = make_nbhd(x, y, z, G);
-      R ref[Q_H], h[Q_H], g[Q_G];
-      shift_refs<S, RULE>(a.phi_prev, idx, nb, walls, ref);
+      const R ref = phi_ref_of<S>(a.phi_prev, idx);
+      R h[Q_H], g[Q_G];
+      load_h<S, RULE, false>(a.h, G.N, idx, nb, walls, a.cd.inv_scale_h, h);
       if (LM == LM_GATHER) {
-        load_h<S, RULE, false>(a.h, G.N, idx, nb, walls, a.cd, ref, h);
-        a.phi_out[idx] = sum_h(h);
+        a.phi_out[idx] = phi_of(h, ref);
       } else {
-        load_pops<S, RULE, false>(a.h, a.g, G.N, idx, nb, walls, a.cd, ref, h, g);
+        load_g<S, RULE, false>(a.g, G.N, idx, nb, walls, a.cd.inv_scale_g, g);
+        // absolute populations: h_i = h'_i + w_i phi_ref
         if (LM == LM_READ_POPS) {
 #pragma unroll
-          for (int i = 0; i < Q_H; ++i) a.out_h[i * G.N + idx] = double(h[i]);
+          for (int i = 0; i < Q_H; ++i) a.out_h[i * G.N + idx] = double(h[i]) + wh(i) * double(ref);
 #pragma unroll
           for (int i = 0; i < Q_G; ++i) a.out_g[i * G.N + idx] = double(g[i]);
         } else {
-          double s = 0;
+          double s = double(ref);
 #pragma unroll
           for (int i = 0; i < Q_H; ++i) s += double(h[i]);
           acc[0] = s;
@@ -921,15 +881,15 @@ struct InitArgs {
   const double* phi0;
   const double* u0;      // may be null
   const double* p0;      // may be null
-  const R* phi_ref;      // R(phi0): the FP16 shift reference of the initial state
+  const R* phi_ref;      // R(phi0): the shift reference of the initial state (shifted forms)
   Geom geo;
   Codec<R> cd;
 };
 
 // Equilibrium initialisation: every fluid cell writes its equilibrium
 // populations where the first step reads them (two buffers: the pull slots;
-// AA: its own slots, the even-step rule), shifted for FP16 storage by the
-// reference that read will use.
+// AA: its own slots, the even-step rule); the shifted forms store them
+// relative to w_i R(phi0) of that cell, the first step's reference.
 template <typename S, bool AA, bool MASK>
 __global__ __launch_bounds__(256) void k_init(InitArgs<S> a) {
   using R = typename Store<S>::R;
@@ -947,25 +907,26 @@ __global__ __launch_bounds__(256) void k_init(InitArgs<S> a) {
   R ux = R(0), uy = R(0), uz = R(0), p = R(0);
   if (a.u0) { ux = R(a.u0[idx]); uy = R(a.u0[G.N + idx]); uz = R(a.u0[2 * G.N + idx]); }
   if (a.p0) p = R(a.p0[idx]);
-  const R base = R(1) - R(1.5) * (ux * ux + uy * uy + uz * uz);
+  const R uu = ux * ux + uy * uy + uz * uz;
+  const R ref = phi_ref_of<S>(a.phi_ref, idx);
   constexpr int RULE = AA ? RULE_AA_EVEN : RULE_AB;
-  R ref[Q_H];
-  shift_refs<S, RULE>(a.phi_ref, idx, nb, walls, ref);
   const unsigned NS = (unsigned)(G.N * (long long)sizeof(S));
+  // h^eq_i - w_i ref = w_i [(phi - ref) + phi (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)]
+  const R dphi = phi - ref;
 #pragma unroll
   for (int i = 0; i < Q_H; ++i) {
     const R cu = dot(ch(i), ux, uy, uz);
-    const R v = R(wh(i)) * phi * (base + cu * (R(3) + R(4.5) * cu));
+    const R v = R(wh(i)) * (dphi + phi * (cu * (R(3) + R(4.5) * cu) - R(1.5) * uu));
     S* q = reinterpret_cast<S*>(pair_base(a.h, G.N, i) + read_off<S, false, RULE>(i, idx, nb, walls, NS));
-    St::st(q, v, St::kShift ? R(wh(i)) * ref[i] : R(0), a.cd.scale_h);
+    St::st(q, v, a.cd.scale_h);
   }
-  const R baseg = p - R(1.5) * (ux * ux + uy * uy + uz * uz);
+  const R baseg = p - R(1.5) * uu;
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) {
     const R cu = dot(cg(i), ux, uy, uz);
     const R v = R(wg(i)) * (baseg + cu * (R(3) + R(4.5) * cu));
     S* q = reinterpret_cast<S*>(pair_base(a.g, G.N, i) + read_off<S, true, RULE>(i, idx, nb, walls, NS));
-    St::st(q, v, R(0), a.cd.scale_g);
+    St::st(q, v, a.cd.scale_g);
   }
 }
 

@@ -202,7 +202,8 @@ Codec<R> make_codec(const pflbm_ctx* c) {
   return cd;
 }
 
-bool shifted(const pflbm_ctx* c) { return c->d.precision == PFLBM_FP32_FP16S; }
+// FP32 and FP16 storage keep h shifted by w_i times a phase field one step old
+bool shifted(const pflbm_ctx* c) { return c->d.precision != PFLBM_FP64; }
 bool is_aa(const pflbm_ctx* c) { return c->d.streaming == PFLBM_STREAM_AA; }
 
 template <typename S> S* pop_h(pflbm_ctx* c, int k) { return reinterpret_cast<S*>(c->ws + c->L.off_h[k]); }
@@ -342,7 +343,7 @@ CellArgs<S> aa_args(pflbm_ctx* c) {
 template <typename S, bool MRT, bool ODD>
 void launch_aa_m(pflbm_ctx* c, const CellArgs<S>& a) {
   using R = typename Store<S>::R;
-  const size_t sm = (size_t)(c->L.bx + 2) * (c->L.by + 2) * 3 * sizeof(R) * (Store<S>::kShift ? 2 : 1);
+  const size_t sm = (size_t)(c->L.bx + 2) * (c->L.by + 2) * 3 * sizeof(R);
   const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
   if (c->d.has_mask) hipLaunchKernelGGL((k_cell_aa<S, MRT, ODD, true>), grd, blk, sm, c->stream, a);
   else hipLaunchKernelGGL((k_cell_aa<S, MRT, ODD, false>), grd, blk, sm, c->stream, a);
@@ -357,8 +358,8 @@ void launch_aa(pflbm_ctx* c, const CellArgs<S>& a, bool odd) {
   }
 }
 
-// phi^{n+1} after an AA step, into the buffer of phi^{n-1}; the writers'
-// phase field phi^n becomes the shift reference
+// phi^{n+1} after an AA step, into the buffer of phi^{n-1}; phi^n becomes the
+// shift reference of the new state
 template <typename S>
 void aa_gather(pflbm_ctx* c) {
   using R = typename Store<S>::R;
@@ -502,7 +503,7 @@ pflbm_status do_init(pflbm_ctx* c, const double* phi0, const double* u0, const d
   a.phi_ref = phi_prev<R>(c);
   a.geo = make_geom(c);
   a.cd = make_codec<R>(c);
-  // FP16 storage: R(phi0) plays phi^{-1}, the shift reference of the initial
+  // shifted forms: R(phi0) plays phi^{-1}, the shift reference of the initial
   // populations
   if (shifted(c)) {
     const unsigned nb = (unsigned)((c->L.N + 255) / 256);
