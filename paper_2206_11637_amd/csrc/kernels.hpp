@@ -22,10 +22,10 @@
 // The fused step kernel k_step gives each block a bx * by tile and a chunk of
 // z planes and marches up the chunk.  The phase field phi^n = sum_i h_i is
 // never read from HBM: for each plane the block pulls the h populations of
-// its cells and of a one-cell ring around the tile, sums them into a 4-plane
-// LDS ring (sentinel for walls and solids), and keeps its own cells' pulled
-// h in registers for the collision one plane later.  The grad/lap stencils
-// read three ring planes.  Pulling the ring cells' h re-reads data that the
+// its cells and of a one-cell ring around the tile and sums them into a
+// 4-plane LDS ring (sentinel for walls and solids); its own cells' pulled h
+// wait in thread-private LDS slots for the collision one plane later.  The
+// grad/lap stencils read three ring planes.  Pulling the ring cells' h re-reads data that the
 // neighbouring tiles read too (mostly from L2).  This needs the second
 // buffer: in place, a neighbouring block could overwrite a ring cell's
 // populations before they are summed.
@@ -414,43 +414,48 @@ __device__ __forceinline__ typename Store<S>::R phi_ref_of(const typename Store<
   return Store<S>::kShift ? phi_prev[idx] : R(0);
 }
 
-// phi^n of the reader of each outgoing population (x + c_i, or x behind a
-// wall or solid), from three stencil planes; only the shifted forms use it.
+// Stencil planes of one cell (below, own, above) in LDS: phi^n of the cell
+// and of its neighbours, the sentinel marking walls and solids.
 template <typename R>
-__device__ __forceinline__ void reader_phis(const R* pm, const R* p0, const R* pp, int TX, int lx,
-                                            int ly, R (&phr)[Q_H]) {
-  const R self = p0[(ly + 1) * TX + lx + 1];
-#pragma unroll
-  for (int i = 0; i < Q_H; ++i) {
+struct Planes {
+  const R* pm;
+  const R* p0;
+  const R* pp;
+  int TX, lx, ly;
+  // phi^n of the reader of outgoing population i (x + c_i, or x behind a wall)
+  __device__ __forceinline__ R reader(int i, R self) const {
+    if (i == 0) return self;
     const Dir d = ch(i);
     const R* pl = d.z < 0 ? pm : (d.z > 0 ? pp : p0);
     const R v = pl[(ly + 1 + d.y) * TX + (lx + 1 + d.x)];
-    phr[i] = (i == 0 || v == sentinel<R>()) ? self : v;
+    return v == sentinel<R>() ? self : v;
   }
-}
+};
 
 // Post-collision value of population i for storage: the deviation h*'_i is
 // relative to w_i phi_ref; the slot must be relative to w_i phi^n(reader).
+// (Read from LDS per population, so no array of reader values stays live.)
 template <typename S>
 __device__ __forceinline__ typename Store<S>::R rebase(int i, typename Store<S>::R v,
                                                        typename Store<S>::R phi_ref,
-                                                       const typename Store<S>::R (&phr)[Q_H]) {
+                                                       typename Store<S>::R self,
+                                                       const Planes<typename Store<S>::R>& pl) {
   using R = typename Store<S>::R;
-  return Store<S>::kShift ? v + R(wh(i)) * (phi_ref - phr[i]) : v;
+  return Store<S>::kShift ? v + R(wh(i)) * (phi_ref - pl.reader(i, self)) : v;
 }
 
 // Two buffers: post-collision values into the cell's own slots.
 template <typename S, bool NT>
 __device__ __forceinline__ void store_own(S* __restrict__ H, S* __restrict__ Gp, long long N,
                                           unsigned idx, const Codec<typename Store<S>::R>& cd,
-                                          typename Store<S>::R phi_ref,
-                                          const typename Store<S>::R (&phr)[Q_H],
+                                          typename Store<S>::R phi_ref, typename Store<S>::R self,
+                                          const Planes<typename Store<S>::R>& pl,
                                           const typename Store<S>::R (&h)[Q_H],
                                           const typename Store<S>::R (&g)[Q_G]) {
   using St = Store<S>;
 #pragma unroll
   for (int i = 0; i < Q_H; ++i)
-    St::template st<NT>(slot(H, N, i, idx), rebase<S>(i, h[i], phi_ref, phr), cd.scale_h);
+    St::template st<NT>(slot(H, N, i, idx), rebase<S>(i, h[i], phi_ref, self, pl), cd.scale_h);
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) St::template st<NT>(slot(Gp, N, i, idx), g[i], cd.scale_g);
 }
@@ -460,8 +465,8 @@ template <typename S, bool ODD, bool NT>
 __device__ __forceinline__ void store_aa(S* __restrict__ H, S* __restrict__ Gp, long long N,
                                          unsigned idx, const Nbhd& nb, unsigned walls,
                                          const Codec<typename Store<S>::R>& cd,
-                                         typename Store<S>::R phi_ref,
-                                         const typename Store<S>::R (&phr)[Q_H],
+                                         typename Store<S>::R phi_ref, typename Store<S>::R self,
+                                         const Planes<typename Store<S>::R>& pl,
                                          const typename Store<S>::R (&h)[Q_H],
                                          const typename Store<S>::R (&g)[Q_G]) {
   using St = Store<S>;
@@ -474,7 +479,7 @@ __device__ __forceinline__ void store_aa(S* __restrict__ H, S* __restrict__ Gp, 
       if (!(walls & (1u << nb27(d.x, d.y, d.z)))) off = pair_off<S>(i, nb.at(d.x, d.y, d.z), NS);
     }
     S* p = reinterpret_cast<S*>(pair_base(H, N, i) + off);
-    St::template st<NT>(p, rebase<S>(i, h[i], phi_ref, phr), cd.scale_h);
+    St::template st<NT>(p, rebase<S>(i, h[i], phi_ref, self, pl), cd.scale_h);
   }
 #pragma unroll
   for (int i = 0; i < Q_G; ++i) {
@@ -493,8 +498,11 @@ __device__ __forceinline__ void store_aa(S* __restrict__ H, S* __restrict__ Gp, 
 #ifndef PFLBM_F64_WAVES
 #define PFLBM_F64_WAVES 1
 #endif
+#ifndef PFLBM_F32_WAVES
+#define PFLBM_F32_WAVES 3
+#endif
 template <typename S>
-struct StepWaves { static constexpr int value = sizeof(S) == 8 ? PFLBM_F64_WAVES : 3; };
+struct StepWaves { static constexpr int value = sizeof(S) == 8 ? PFLBM_F64_WAVES : PFLBM_F32_WAVES; };
 
 template <typename S>
 struct StepArgs {
@@ -520,9 +528,10 @@ void k_step(StepArgs<S> a) {
   using St = Store<S>;
   using R = typename St::R;
   extern __shared__ unsigned char smem_raw[];
-  R* ring = reinterpret_cast<R*>(smem_raw);     // [4][TY][TX]
   const Geom& G = a.geo;
   const int TX = G.bx + 2, TY = G.by + 2, TXY = TX * TY;
+  R* ring = reinterpret_cast<R*>(smem_raw);     // [4][TY][TX]
+  R* hbuf = ring + 4 * TXY;                     // [2][15][256], thread-private slots
   const ChunkCoord t = chunk_of_block(G);
   const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + ly * G.bx;
   const int x = t.x0 + lx, y = t.y0 + ly;
@@ -550,9 +559,10 @@ void k_step(StepArgs<S> a) {
   }
   const unsigned sxy = (unsigned)G.nx * (unsigned)G.ny;
 
-  // phi^n of plane p (own position kept: pulled h, its reference, walls,
-  // solid flag)
-  R hn[Q_H];
+  // phi^n of plane p into the ring (own position: also its reference, walls
+  // and solid flag for the collision one plane later, and its pulled h in a
+  // thread-private LDS slot of the plane's parity: no registers held across
+  // the plane, no second pull)
   R refn = R(0);
   unsigned wn = 0;
   bool sn = true;
@@ -567,10 +577,14 @@ void k_step(StepArgs<S> a) {
       bool sol;
       wn = cell_walls<MASK>(ox, oy, pz, idx, G, a.nbr, sol);
       if (!sol) {
+        R hh[Q_H];
         refn = phi_ref_of<S>(a.phi_prev, idx);
-        load_h<S, RULE_AB, kNtPull>(a.h_in, G.N, idx, make_nbhd(ox, oy, pz, G), wn, a.cd.inv_scale_h, hn);
-        v = phi_of(hn, refn);
+        load_h<S, RULE_AB, kNtPull>(a.h_in, G.N, idx, make_nbhd(ox, oy, pz, G), wn, a.cd.inv_scale_h, hh);
+        v = phi_of(hh, refn);
         sn = false;
+        R* hs = hbuf + (p & 1) * (Q_H * 256) + tid;
+#pragma unroll
+        for (int i = 0; i < Q_H; ++i) hs[i * 256] = hh[i];
       }
     }
     rp[opos] = v;
@@ -593,9 +607,6 @@ void k_step(StepArgs<S> a) {
   plane(t.z0 - 1);
   plane(t.z0);
   for (int z = t.z0; z < t.z1; ++z) {
-    R h[Q_H];
-#pragma unroll
-    for (int i = 0; i < Q_H; ++i) h[i] = hn[i];
     const R ref = refn;
     const unsigned walls = wn;
     const bool work = active && !sn;
@@ -606,6 +617,10 @@ void k_step(StepArgs<S> a) {
     plane(z + 1);
     __syncthreads();
     if (work) {
+      R h[Q_H];
+      const R* hs = hbuf + (z & 1) * (Q_H * 256) + tid;
+#pragma unroll
+      for (int i = 0; i < Q_H; ++i) h[i] = hs[i * 256];
       const R* pm = ring + ((z - 1) & 3) * TXY;
       const R* p0 = ring + (z & 3) * TXY;
       const R* pp = ring + ((z + 1) & 3) * TXY;
@@ -619,12 +634,9 @@ void k_step(StepArgs<S> a) {
       prologue(phi, sum_h(h), g, Gx, Gy, Gz, lap, a.P, c);
       collide_g<R, MRT>(g, c, a.P);
       collide_h<R, MRT>(h, c, a.P);
-      R phr[Q_H];
-      if (St::kShift) {
-        reader_phis(pm, p0, pp, TX, lx, ly, phr);
-        a.phi_out[idx] = phi;
-      }
-      store_own<S, kNtStore>(a.h_out, a.g_out, G.N, idx, a.cd, ref, phr, h, g);
+      if (St::kShift) a.phi_out[idx] = phi;
+      const Planes<R> pl{pm, p0, pp, TX, lx, ly};
+      store_own<S, kNtStore>(a.h_out, a.g_out, G.N, idx, a.cd, ref, phi, pl, h, g);
     }
   }
 }
@@ -693,9 +705,8 @@ void k_cell_aa(CellArgs<S> a) {
   prologue(phi, sum_h(h), g, Gx, Gy, Gz, lap, a.P, c);
   collide_g<R, MRT>(g, c, a.P);
   collide_h<R, MRT>(h, c, a.P);
-  R phr[Q_H];
-  if (St::kShift) reader_phis(pm, p0, pp, TX, lx, ly, phr);
-  store_aa<S, ODD, AaPolicy<ODD>::nt_store>(a.h, a.g, G.N, idx, nb, walls, a.cd, ref, phr, h, g);
+  const Planes<R> pl{pm, p0, pp, TX, lx, ly};
+  store_aa<S, ODD, AaPolicy<ODD>::nt_store>(a.h, a.g, G.N, idx, nb, walls, a.cd, ref, phi, pl, h, g);
 }
 
 // Cell moments phi, u, p* of the current state with the step's force

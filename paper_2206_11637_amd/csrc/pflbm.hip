@@ -255,7 +255,8 @@ StepArgs<S> step_args(pflbm_ctx* c) {
 template <typename S>
 void launch_step(pflbm_ctx* c, const StepArgs<S>& a) {
   using R = typename Store<S>::R;
-  const size_t sm = (size_t)4 * (c->L.bx + 2) * (c->L.by + 2) * sizeof(R);
+  // 4-plane phi ring + two planes of the threads' own h
+  const size_t sm = ((size_t)4 * (c->L.bx + 2) * (c->L.by + 2) + 2 * Q_H * 256) * sizeof(R);
   const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks_step);
   const bool mrt = c->d.collision == PFLBM_MRT, m = c->d.has_mask;
   if (mrt) {
