@@ -358,8 +358,14 @@ struct AdjArgs {
   Codec<R> cd;
 };
 
+#ifndef PFLBM_ADJ_WAVES
+#define PFLBM_ADJ_WAVES 3
+#endif
+template <typename S>
+struct AdjWaves { static constexpr int value = sizeof(S) == 8 ? 1 : PFLBM_ADJ_WAVES; };
+
 template <typename S, bool MRT, int RULE, bool MASK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<S>::value)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjWaves<S>::value)))
 void k_adj_cell(AdjArgs<S> a) {
   using St = Store<S>;
   using R = typename St::R;
