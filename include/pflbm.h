@@ -182,8 +182,19 @@ pflbm_status pflbm_load_state(pflbm_ctx* ctx, const void* d_src, int64_t step_co
 /* One time step from a saved state of level n (d_src, as written by
  * pflbm_save_state) into another, non-overlapping buffer of the same size
  * (d_dst, level n + 1), without touching the context's own state; used to
- * recompute checkpoint segments without copies.  Asynchronous. */
-pflbm_status pflbm_step_states(pflbm_ctx* ctx, const void* d_src, void* d_dst, int64_t n);
+ * recompute checkpoint segments without copies.  Asynchronous.
+ * flags (PFLBM_STREAM_AB contexts only; PFLBM_ERR_ARG otherwise), for a chain
+ * of such steps:
+ *   PFLBM_STATES_WRITE_SRC_PHI  the step also writes the phi^n it forms into
+ *                               d_src's phi^n slot (d_src is then written);
+ *   PFLBM_STATES_SKIP_DST_PHI   d_dst's phi^{n+1} slot is left unformed (a
+ *                               following step from d_dst with
+ *                               PFLBM_STATES_WRITE_SRC_PHI fills it); saves one
+ *                               pass over h per step.
+ * Without flags d_src is only read and d_dst is complete. */
+#define PFLBM_STATES_WRITE_SRC_PHI 1
+#define PFLBM_STATES_SKIP_DST_PHI 2
+pflbm_status pflbm_step_states(pflbm_ctx* ctx, void* d_src, void* d_dst, int64_t n, int32_t flags);
 
 /* Steps taken since the last init or load. */
 int64_t pflbm_step_count(const pflbm_ctx* ctx);

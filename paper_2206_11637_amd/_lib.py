@@ -11,6 +11,7 @@ PFLBM_OK, PFLBM_ERR_ARG, PFLBM_ERR_STATE, PFLBM_ERR_HIP, PFLBM_ERR_UNSTABLE, \
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16s": 2}
 COLLISIONS = {"bgk": 0, "mrt": 1}
 STREAMING = {"ab": 0, "aa": 1}
+STATES_WRITE_SRC_PHI, STATES_SKIP_DST_PHI = 1, 2
 
 
 class Desc(C.Structure):
@@ -44,7 +45,7 @@ SIGNATURES = {
     "pflbm_state_bytes": (C.c_size_t, [C.c_void_p]),
     "pflbm_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pflbm_load_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
-    "pflbm_step_states": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "pflbm_step_states": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
     "pflbm_step_count": (C.c_int64, [C.c_void_p]),
     "pflbm_profile_step": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double)]),
     "pflbm_sync": (C.c_int, [C.c_void_p]),

@@ -17,7 +17,8 @@
 //                apply its vector-Jacobian product; writes lam^n, the stencil
 //                adjoints s(x) = (dL/d grad phi, dL/d lap phi) and FP64 block
 //                sums of dL/domega_phi and dL/dsigma.
-//   k_adj_stencil  a_phi^n(y) = sum over valid neighbours m of
+//   k_adj_stencil  (z-marching like the forward step)
+//                a_phi^n(y) = sum over valid neighbours m of
 //                -3 w_m c_m . (s_G(y + c_m) + s_G(y)) + 6 w_m (s_L(y + c_m) - s_L(y)),
 //                the transpose of grad phi = 3 sum w c (phi_m - phi) and
 //                lap phi = 6 sum w (phi_m - phi) with the wall rule.
@@ -456,56 +457,89 @@ struct AdjStencilArgs {
 };
 
 // a_phi(y) = sum_m valid(y, m) [-3 w_m c_m.(s_G(y+c_m) + s_G(y)) + 6 w_m (s_L(y+c_m) - s_L(y))]
+// Marching in z like the forward step: each block owns a tile and a chunk of
+// planes and keeps the stencil adjoints of 4 planes (tile + one-cell ring) in
+// an LDS ring, so every value is read from memory about once.
 template <typename R, bool MASK>
 __global__ __launch_bounds__(256) void k_adj_stencil(AdjStencilArgs<R> a) {
   extern __shared__ unsigned char smem_raw[];
   const Geom& G = a.geo;
-  const int TX = G.bx + 2, TY = G.by + 2, total = TX * TY * 3;
-  R* ts = reinterpret_cast<R*>(smem_raw);                       // [4][total]
-  unsigned char* tv = reinterpret_cast<unsigned char*>(ts + 4 * total);   // validity
-  const TileCoord t = tile_of_block(G);
-  const int tid = threadIdx.x + threadIdx.y * G.bx;
-  for (int e = tid; e < total; e += 256) {
-    const int ix = e % TX, r = e / TX, iy = r % TY, iz = r / TY;
-    int X = t.x0 - 1 + ix, Y = t.y0 - 1 + iy, Z = t.z - 1 + iz;
-    unsigned char ok = 0;
+  const int TX = G.bx + 2, TY = G.by + 2, TXY = TX * TY;
+  R* ts = reinterpret_cast<R*>(smem_raw);                                // [4 slots][4][TXY]
+  unsigned char* tv = reinterpret_cast<unsigned char*>(ts + 16 * TXY);   // [4 slots][TXY] validity
+  const ChunkCoord t = chunk_of_block(G);
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + ly * G.bx;
+  const int x = t.x0 + lx, y = t.y0 + ly;
+  const bool active = x < G.nx && y < G.ny;
+  int ox = x, oy = y;
+  const bool own_ok = wrap(ox, G.nx, G.px) && wrap(oy, G.ny, G.py);
+  const int opos = (ly + 1) * TX + lx + 1;
+  const int NH = 2 * TX + 2 * G.by;
+  int hpos = 0, hx = 0, hy = 0;
+  bool halo_ok = false;
+  if (tid < NH) {
+    int ix, iy;
+    if (tid < TX) { ix = tid; iy = 0; }
+    else if (tid < 2 * TX) { ix = tid - TX; iy = TY - 1; }
+    else if (tid < 2 * TX + G.by) { ix = 0; iy = 1 + tid - 2 * TX; }
+    else { ix = TX - 1; iy = 1 + tid - 2 * TX - G.by; }
+    hpos = iy * TX + ix;
+    hx = t.x0 - 1 + ix;
+    hy = t.y0 - 1 + iy;
+    halo_ok = wrap(hx, G.nx, G.px) && wrap(hy, G.ny, G.py);
+  }
+  const unsigned sxy = (unsigned)G.nx * (unsigned)G.ny;
+  auto fill = [&](int slotk, int pos, bool ok, int X, int Y, int Z) {
     R v0 = R(0), v1 = R(0), v2 = R(0), v3 = R(0);
-    if (wrap(X, G.nx, G.px) && wrap(Y, G.ny, G.py) && wrap(Z, G.nz, G.pz)) {
-      const unsigned id = X + (unsigned)G.nx * (Y + (unsigned)G.ny * Z);
+    unsigned char valid = 0;
+    if (ok) {
+      const unsigned id = X + G.nx * Y + sxy * Z;
       if (!MASK || !a.mask[id]) {
-        ok = 1;
+        valid = 1;
         v0 = *slot(a.sadj, G.N, 0, id);
         v1 = *slot(a.sadj, G.N, 1, id);
         v2 = *slot(a.sadj, G.N, 2, id);
         v3 = *slot(a.sadj, G.N, 3, id);
       }
     }
-    ts[e] = v0;
-    ts[total + e] = v1;
-    ts[2 * total + e] = v2;
-    ts[3 * total + e] = v3;
-    tv[e] = ok;
-  }
-  __syncthreads();
-  const int lx = threadIdx.x, ly = threadIdx.y;
-  const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
-  if (x >= G.nx || y >= G.ny) return;
-  const int c0 = (TY + ly + 1) * TX + lx + 1;
-  if (!tv[c0]) return;
-  const R sx = ts[c0], sy = ts[total + c0], sz = ts[2 * total + c0], sl = ts[3 * total + c0];
-  R acc = R(0);
+    R* b = ts + slotk * 4 * TXY;
+    b[pos] = v0;
+    b[TXY + pos] = v1;
+    b[2 * TXY + pos] = v2;
+    b[3 * TXY + pos] = v3;
+    tv[slotk * TXY + pos] = valid;
+  };
+  auto plane = [&](int p) {
+    int pz = p;
+    const bool zok = wrap(pz, G.nz, G.pz);
+    fill(p & 3, opos, own_ok && zok, ox, oy, pz);
+    if (tid < NH) fill(p & 3, hpos, halo_ok && zok, hx, hy, pz);
+  };
+  plane(t.z0 - 1);
+  plane(t.z0);
+  for (int z = t.z0; z < t.z1; ++z) {
+    plane(z + 1);
+    __syncthreads();
+    const int sm = (z - 1) & 3, s0 = z & 3, sp = (z + 1) & 3;
+    if (active && tv[s0 * TXY + opos]) {
+      const R* c0 = ts + s0 * 4 * TXY;
+      const R sx = c0[opos], sy = c0[TXY + opos], sz = c0[2 * TXY + opos], sl = c0[3 * TXY + opos];
+      R acc = R(0);
 #pragma unroll
-  for (int k = 1; k < 27; ++k) {
-    const Dir d = cg(k);
-    const int e = ((1 + d.z) * TY + (ly + 1 + d.y)) * TX + (lx + 1 + d.x);
-    if (tv[e]) {
-      const R w = R(wg(k));
-      const R gsum = dot(d, ts[e] + sx, ts[total + e] + sy, ts[2 * total + e] + sz);
-      acc += R(-3) * w * gsum + R(6) * w * (ts[3 * total + e] - sl);
+      for (int k = 1; k < 27; ++k) {
+        const Dir d = cg(k);
+        const int sk = d.z < 0 ? sm : (d.z > 0 ? sp : s0);
+        const int e = (ly + 1 + d.y) * TX + (lx + 1 + d.x);
+        if (tv[sk * TXY + e]) {
+          const R* b = ts + sk * 4 * TXY;
+          const R w = R(wg(k));
+          const R gsum = dot(d, b[e] + sx, b[TXY + e] + sy, b[2 * TXY + e] + sz);
+          acc += R(-3) * w * gsum + R(6) * w * (b[3 * TXY + e] - sl);
+        }
+      }
+      a.aphi_out[x + G.nx * y + sxy * z] = acc;
     }
   }
-  const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
-  a.aphi_out[idx] = acc;
 }
 
 // a_phi += dL/dphi (FP64 input)

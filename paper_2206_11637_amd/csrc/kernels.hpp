@@ -513,6 +513,7 @@ struct StepArgs {
   S* g_out;
   const R* phi_prev;         // phi^{n-1}: shift reference of state n (shifted forms)
   R* phi_out;                // phi^n, the reference of state n + 1 (shifted forms)
+  R* phi_src_out;            // phi^n into the read state's phi slot (may be null)
   const unsigned* nbr;       // solid-neighbour bits (mask only)
   Geom geo;
   Phys<R> P;
@@ -635,6 +636,7 @@ void k_step(StepArgs<S> a) {
       collide_g<R, MRT>(g, c, a.P);
       collide_h<R, MRT>(h, c, a.P);
       if (St::kShift) a.phi_out[idx] = phi;
+      if (a.phi_src_out) a.phi_src_out[idx] = phi;
       const Planes<R> pl{pm, p0, pp, TX, lx, ly};
       store_own<S, kNtStore>(a.h_out, a.g_out, G.N, idx, a.cd, ref, phi, pl, h, g);
     }

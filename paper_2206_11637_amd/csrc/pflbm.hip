@@ -245,6 +245,7 @@ StepArgs<S> step_args(pflbm_ctx* c) {
   a.g_out = pop_g<S>(c, c->pcur ^ 1);
   a.phi_prev = phi_prev<R>(c);
   a.phi_out = shifted(c) ? phi_buf<R>(c, c->iprev ^ 1) : nullptr;
+  a.phi_src_out = nullptr;
   a.nbr = nbr_ptr(c);
   a.geo = make_geom(c);
   a.P = make_phys<R>(c->p);
@@ -413,9 +414,9 @@ pflbm_status do_steps(pflbm_ctx* c, int64_t n) {
 //       exactly once, so dst needs no copy of src), phi^{n+1} is gathered with
 //       the writers' phi^n from src, and src's phi^n becomes dst's reference.
 template <typename S>
-pflbm_status do_step_states(pflbm_ctx* c, const void* src, void* dst, int64_t n) {
+pflbm_status do_step_states(pflbm_ctx* c, void* src, void* dst, int64_t n, int32_t flags) {
   using R = typename Store<S>::R;
-  const char* s = static_cast<const char*>(src);
+  char* s = static_cast<char*>(src);
   char* d = static_cast<char*>(dst);
   const StateView v = state_view(c);
   const S* hs = reinterpret_cast<const S*>(s + v.oh);
@@ -434,9 +435,10 @@ pflbm_status do_step_states(pflbm_ctx* c, const void* src, void* dst, int64_t n)
     a.g_out = gd;
     a.phi_prev = shifted(c) ? reinterpret_cast<const R*>(s + v.oprev) : nullptr;
     a.phi_out = shifted(c) ? reinterpret_cast<R*>(d + v.oprev) : nullptr;
+    if (flags & PFLBM_STATES_WRITE_SRC_PHI) a.phi_src_out = reinterpret_cast<R*>(s + v.ophi);
     launch_step<S>(c, a);
     b.phi_prev = a.phi_out;
-    launch_light<S, LM_GATHER>(c, b, RULE_AB);
+    if (!(flags & PFLBM_STATES_SKIP_DST_PHI)) launch_light<S, LM_GATHER>(c, b, RULE_AB);
   } else {
     CellArgs<S> a = aa_args<S>(c);
     a.h_in = hs;
@@ -794,11 +796,14 @@ pflbm_status pflbm_load_state(pflbm_ctx* c, const void* src, int64_t step_count)
   return check_hip(c, e, "pflbm_load_state");
 }
 
-pflbm_status pflbm_step_states(pflbm_ctx* c, const void* src, void* dst, int64_t n) {
+pflbm_status pflbm_step_states(pflbm_ctx* c, void* src, void* dst, int64_t n, int32_t flags) {
   if (!c) return PFLBM_ERR_ARG;
   if (!src || !dst || src == dst || n < 0) return fail(c, PFLBM_ERR_ARG, "bad state buffers or step index");
+  if (flags & ~(PFLBM_STATES_WRITE_SRC_PHI | PFLBM_STATES_SKIP_DST_PHI))
+    return fail(c, PFLBM_ERR_ARG, "unknown pflbm_step_states flags");
+  if (flags && is_aa(c)) return fail(c, PFLBM_ERR_ARG, "pflbm_step_states flags need PFLBM_STREAM_AB");
   if (c->d.has_mask && !c->mask_set) return fail(c, PFLBM_ERR_STATE, "mask not set");
-  DISPATCH(c, do_step_states, c, src, dst, n);
+  DISPATCH(c, do_step_states, c, src, dst, n, flags);
 }
 
 int64_t pflbm_step_count(const pflbm_ctx* c) { return c ? c->steps : -1; }

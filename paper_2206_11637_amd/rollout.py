@@ -19,6 +19,8 @@ from typing import Optional
 
 import torch
 
+from . import _lib
+
 
 @dataclasses.dataclass
 class RolloutSpec:
@@ -95,12 +97,21 @@ class PFLBMRollout(torch.autograd.Function):
         # segment buffer: slot 0 is the checkpoint itself, slots 1..S-1 are
         # recomputed out of place from the previous slot (no state copies)
         seg = torch.empty((max(S - 1, 1), sim.state_bytes()), dtype=torch.uint8, device=sim.device)
+        # two-buffer contexts chain the recompute: each step writes the phase
+        # field it forms into the state it read and leaves the next state's to
+        # the following step (the last step of a segment forms it itself)
+        chain = getattr(sim, "streaming", "ab") == "ab"
         starts = sorted(ckpt)
         for a in reversed(starts):
             b = min(a + S, N)
             states = [ckpt[a]]
             for n in range(a, b - 1):
-                sim.step_states(states[-1], seg[n - a], n)
+                flags = 0
+                if chain:
+                    flags = _lib.STATES_WRITE_SRC_PHI
+                    if n < b - 2:
+                        flags |= _lib.STATES_SKIP_DST_PHI
+                sim.step_states(states[-1], seg[n - a], n, flags)
                 states.append(seg[n - a])
             for n in range(b - 1, a - 1, -1):
                 inject(n + 1)

@@ -50,6 +50,7 @@ class Simulation:
     def __init__(self, nx: int, ny: int, nz: int, periodic=(True, False, True),
                  precision: str = "fp32", collision: str = "mrt", solid=None, params=None,
                  device: str = "cuda:0", streaming: str = "ab"):
+        self.streaming = streaming
         self.lib = load()
         self.device = torch.device(device)
         self.shape = (nz, ny, nx)
@@ -155,10 +156,11 @@ class Simulation:
         check(self.lib.pflbm_load_state(self.ctx, _ptr(buf), int(step_count)), self.ctx,
               "pflbm_load_state")
 
-    def step_states(self, src: torch.Tensor, dst: torch.Tensor, n: int) -> None:
-        """One step from saved state `src` (level n) into buffer `dst` (level n + 1)."""
-        check(self.lib.pflbm_step_states(self.ctx, _ptr(src), _ptr(dst), int(n)), self.ctx,
-              "pflbm_step_states")
+    def step_states(self, src: torch.Tensor, dst: torch.Tensor, n: int, flags: int = 0) -> None:
+        """One step from saved state `src` (level n) into buffer `dst` (level
+        n + 1); flags as in pflbm.h (write src's phi, leave dst's phi unformed)."""
+        check(self.lib.pflbm_step_states(self.ctx, _ptr(src), _ptr(dst), int(n), int(flags)),
+              self.ctx, "pflbm_step_states")
 
     def profile_step(self, n: int):
         """Steps n times under HIP events; returns milliseconds

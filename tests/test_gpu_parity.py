@@ -244,3 +244,37 @@ def test_both_streaming_schemes_give_identical_results(precision):
             assert torch.equal(x, y)
         for x, y in zip(a.populations(), b.populations()):
             assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16s"])
+def test_chained_state_steps_fill_every_phase_field(precision):
+    """The checkpoint recompute's chain (each step writes the phi it forms into
+    the state it read and skips the next state's gather; the last one gathers)
+    leaves every state identical to one saved from the running context."""
+    from paper_2206_11637_amd._lib import (PFLBMError, STATES_SKIP_DST_PHI,
+                                           STATES_WRITE_SRC_PHI)
+    wl = W.random_state(70, 21, 13, periodic=(True, False, True), solid_fraction=0.05, seed=10)
+    say(f"case: chained step_states {precision}")
+    sim = _sim(wl, precision)
+    N = wl.nx * wl.ny * wl.nz
+    fluid = torch.from_numpy(~np.asarray(wl.solid, dtype=bool).reshape(-1)).to(sim.device)
+    sim.step(2)
+    states = [sim.save_state()]
+    refs = [states[0].clone()]
+    for n in range(2, 6):
+        states.append(torch.full_like(states[0], 0xFF))
+        flags = STATES_WRITE_SRC_PHI | (STATES_SKIP_DST_PHI if n < 5 else 0)
+        sim.step_states(states[-2], states[-1], n, flags)
+        sim.step(1)
+        refs.append(sim.save_state())
+    for k, (a, b) in enumerate(zip(states, refs)):
+        a, b = _split_state(a, N, precision), _split_state(b, N, precision)
+        assert torch.equal(a[0][:, fluid], b[0][:, fluid]), ("h", k)
+        assert torch.equal(a[1][:, fluid], b[1][:, fluid]), ("g", k)
+        assert torch.equal(a[2][fluid], b[2][fluid]), ("phi", k)
+        if precision != "fp64":
+            assert torch.equal(a[3][fluid], b[3][fluid]), ("phi_prev", k)
+    aa = _sim(wl, precision, streaming="aa")
+    buf = aa.save_state()
+    with pytest.raises(PFLBMError):
+        aa.step_states(buf, torch.empty_like(buf), 0, STATES_WRITE_SRC_PHI)
