@@ -162,10 +162,12 @@ def test_config3_gradients_match_central_differences_fp64():
 
 
 @pytest.mark.parametrize("streaming", ["ab", "aa"])
-@pytest.mark.parametrize("precision,tol", [("fp32", 0.25), ("fp16s", 1.0)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-3), ("fp16s", 0.2)])
 def test_reduced_precision_gradients_track_fp64(precision, tol, streaming):
     """FP32 arithmetic (FP32 or FP16 storage) forward + FP32 adjoint with FP64
-    parameter-gradient sums, against the FP64 gradients (errors reported)."""
+    parameter-gradient sums, against the FP64 gradients.  Measured with the
+    shifted storage: FP32 ~1e-5 relative, FP16 storage ~4e-2 (dM) and 1e-3
+    (dsigma); the bounds leave a margin of ~5-100x."""
     wl = W.config3()
     N, K = 400, 10
     say(f"case: config3 {precision} {streaming} gradients vs fp64 over {N} steps")

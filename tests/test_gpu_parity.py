@@ -130,7 +130,9 @@ def test_translation_invariance_is_bitwise(precision, streaming):
 def test_mass_conserved_on_gpu_all_precisions(streaming):
     wl = W.config4(scale=8)   # tube mask, walls
     say(f"case: mass conservation taylor tube /8 {streaming}")
-    for precision, tol in (("fp64", 1e-13), ("fp32", 2e-6), ("fp16s", 1e-3)):
+    # FP32 and FP16 storage keep h shifted (w_i phi of the reader), so the
+    # rounding acts on the deviations: measured 9e-11 and 4e-7 over 100 steps
+    for precision, tol in (("fp64", 1e-13), ("fp32", 1e-9), ("fp16s", 1e-5)):
         sim = _sim(wl, precision, streaming=streaming)
         r0 = sim.reduce()
         sim.step(100)
@@ -141,10 +143,11 @@ def test_mass_conserved_on_gpu_all_precisions(streaming):
 
 
 @pytest.mark.parametrize("streaming", STREAMING)
-@pytest.mark.parametrize("precision,tol_phi", [("fp32", 1e-4), ("fp16s", 5e-4)])
+@pytest.mark.parametrize("precision,tol_phi", [("fp32", 1e-6), ("fp16s", 2e-4)])
 def test_reduced_precision_forms_track_fp64(precision, tol_phi, streaming):
     """FP32 and FP16-storage forms against the FP64 path on the capillary
-    wave (errors reported; bounds set from the rounding units)."""
+    wave after 200 steps (measured max|dphi| 7.6e-8 FP32, 4.2e-5 FP16
+    storage; the bounds leave a margin of ~5-10x)."""
     wl = W.config0()
     say(f"case: config0 {precision} {streaming} vs fp64")
     ref = _sim(wl, "fp64")
