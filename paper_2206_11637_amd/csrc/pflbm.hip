@@ -383,7 +383,7 @@ void one_step(pflbm_ctx* c, hipEvent_t mid = nullptr) {
     return;
   }
   launch_aa<S>(c, aa_args<S>(c), c->steps & 1);
-  if (mid) hipEventRecord(mid, c->stream);
+  if (mid) (void)hipEventRecord(mid, c->stream);
   c->steps += 1;
   aa_gather<S>(c);
 }
@@ -465,27 +465,27 @@ pflbm_status do_profile(pflbm_ctx* c, int64_t n, double* out_ms) {
   std::vector<hipEvent_t> ev((size_t)(2 * n + 1));
   for (auto& e : ev)
     if (pflbm_status s = check_hip(c, hipEventCreate(&e), "pflbm_profile_step event")) return s;
-  hipEventRecord(ev[0], c->stream);
+  (void)hipEventRecord(ev[0], c->stream);
   for (int64_t s = 0; s < n; ++s) {
     one_step<S>(c, ev[2 * s + 1]);
-    if (!is_aa(c)) hipEventRecord(ev[2 * s + 1], c->stream);
-    hipEventRecord(ev[2 * s + 2], c->stream);
+    if (!is_aa(c)) (void)hipEventRecord(ev[2 * s + 1], c->stream);
+    (void)hipEventRecord(ev[2 * s + 2], c->stream);
   }
   pflbm_status st = check_hip(c, hipEventSynchronize(ev[2 * n]), "pflbm_profile_step");
   double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t s = 0; s < n && !st; ++s) {
     float t0 = 0.f, t1 = 0.f;
-    hipEventElapsedTime(&t0, ev[2 * s], ev[2 * s + 1]);
-    hipEventElapsedTime(&t1, ev[2 * s + 1], ev[2 * s + 2]);
+    (void)hipEventElapsedTime(&t0, ev[2 * s], ev[2 * s + 1]);
+    (void)hipEventElapsedTime(&t1, ev[2 * s + 1], ev[2 * s + 2]);
     acc[0] += t0;
     acc[1] += t1;
   }
   if (!st && n > 0) {
     float t = 0.f;
-    hipEventElapsedTime(&t, ev[0], ev[2 * n]);
+    (void)hipEventElapsedTime(&t, ev[0], ev[2 * n]);
     acc[2] = t;
   }
-  for (auto& e : ev) hipEventDestroy(e);
+  for (auto& e : ev) (void)hipEventDestroy(e);
   for (int k = 0; k < 3; ++k) out_ms[k] = acc[k];
   if (st) return st;
   return check_hip(c, hipGetLastError(), "pflbm_profile_step");
