@@ -238,8 +238,8 @@ pflbm_status pflbm_adjoint_inject_phi(pflbm_ctx* ctx, const double* d_dl_dphi);
 
 /* One reverse step: lambda^{n+1} -> lambda^n through the step n -> n+1,
  * using the primal state of level n (a buffer written by pflbm_save_state
- * when the step count was n), and adds this step's contributions to dL/dM
- * and dL/dsigma. */
+ * when the step count was n, or by pflbm_step_states with its phi^n formed),
+ * and adds this step's contributions to dL/dM and dL/dsigma. */
 pflbm_status pflbm_adjoint_step(pflbm_ctx* ctx, const void* d_state_n, int64_t n);
 
 /* Reverse of pflbm_init_equilibrium for phi0: d_dphi0 [N] (FP64) receives

@@ -82,6 +82,20 @@ def test_parameter_validation_without_a_gpu():
     assert lib.pflbm_set_params(ctx, C.byref(p)) == L.PFLBM_ERR_ARG
     # stepping before init is a state error, not a crash
     assert lib.pflbm_step(ctx, 1) == L.PFLBM_ERR_STATE
+    # saved-state steps: bad buffers and unknown flags are rejected on the host
+    a, b = C.c_void_p(1 << 20), C.c_void_p(1 << 21)
+    assert lib.pflbm_step_states(ctx, a, a, 0, 0) == L.PFLBM_ERR_ARG
+    assert lib.pflbm_step_states(ctx, a, b, -1, 0) == L.PFLBM_ERR_ARG
+    assert lib.pflbm_step_states(ctx, a, b, 0, 4) == L.PFLBM_ERR_ARG
+    assert lib.pflbm_set_check_interval(ctx, -1) == L.PFLBM_ERR_ARG
+    assert lib.pflbm_destroy(ctx) == 0
+    # the chained-recompute flags need the two-buffer scheme
+    daa = L.Desc(8, 8, 8, 7, 1, 1, 0, L.STREAMING["aa"])
+    n = lib.pflbm_workspace_bytes(C.byref(daa))
+    ctx = C.c_void_p()
+    assert lib.pflbm_create(C.byref(daa), C.c_void_p(4096), n, None, C.byref(ctx)) == 0
+    assert lib.pflbm_step_states(ctx, a, b, 0, L.STATES_WRITE_SRC_PHI) == L.PFLBM_ERR_ARG
+    assert "PFLBM_STREAM_AB" in lib.pflbm_last_error(ctx).decode()
     assert lib.pflbm_destroy(ctx) == 0
 
 
