@@ -252,6 +252,14 @@ def main():
         form("fp32_drop_impact_384^3", time_form, wl2, "fp32", half, args.warmup)
         form("fp16s_drop_impact_384^3", time_form, wl2, "fp16s", half, args.warmup)
         form("precision_errors_drop_impact_384^3", precision_errors, wl2)
+        # one GPU's share of the 384^3 drop on 8 GPUs (z-slabs of 48 planes
+        # through the drop; z wraps where the slab exchange would be)
+        z0 = 192 - 24
+        shard = W.Workload("drop_impact_shard_384x384x48", 384, 384, 48, (True, False, True),
+                           wl2.params, wl2.phi0[z0:z0 + 48].copy(), wl2.u0[:, z0:z0 + 48].copy(),
+                           wl2.pstar0[z0:z0 + 48].copy(), None, wl2.steps)
+        form("fp32_shard_384x384x48_of_drop_impact", time_form, shard, "fp32", half, args.warmup)
+        del shard
         del wl2
         # the benchmark's M = 0.01 impact goes unstable after ~1.1k steps in
         # every precision; the 5000-step growth of the errors runs at M = 0.03

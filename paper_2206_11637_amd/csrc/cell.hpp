@@ -169,98 +169,119 @@ __device__ __forceinline__ R hermite2(Dir d, const Sym<R>& A) {
   return r;
 }
 
-// S12-S13: hydrodynamic collision in place.  Each opposite pair (i, i+1) is
-// done together: the equilibrium and the projection split into a part even
-// in c (shared) and a part odd in c (sign-flipped); the forcing term is odd.
+// d^T B d for a lattice direction d (components in {-1, 0, 1}) and symmetric
+// B, with the off-diagonals passed doubled (t = 2 B_ab): a face picks one
+// diagonal entry, an edge two plus one off-diagonal, a corner all six.
+template <typename R>
+__device__ __forceinline__ R quad(Dir d, const Sym<R>& B, R txy, R txz, R tyz) {
+  R r = R(0);
+  if (d.x) r += B.xx;
+  if (d.y) r += B.yy;
+  if (d.z) r += B.zz;
+  if (d.x * d.y) r += (d.x * d.y > 0) ? txy : -txy;
+  if (d.x * d.z) r += (d.x * d.z > 0) ? txz : -txz;
+  if (d.y * d.z) r += (d.y * d.z > 0) ? tyz : -tyz;
+  return r;
+}
+
+// One relaxation with projected MRT and Guo forcing, folded per opposite pair.
+// With f^eq_i = w_i [e + 3 c.u' + 9/2 (c.u')^2 - 3/2 u'.u'] the post-collision
+//   f*_i = f_i + s_hi (f^eq_i - f_i) + (s_lo - s_hi) (P Delta)_i + forcing_i
+// splits into a part even in c,  w_i [e0 + 9/2 c^T B c]  with
+//   B = s_hi u u^T + (s_lo - s_hi) A2,  e0 = s_hi e - 3/2 s_hi u.u - 3/2 (s_lo - s_hi) tr A2,
+// and a part odd in c,  w_i c.V  with  V = 3 s_hi u + 3 (s_lo - s_hi) a1 + forcing vector,
+// so f*_i = (1 - s_hi) f_i + even_i + odd_i and f*_{i+1} = (1 - s_hi) f_{i+1} + even_i - odd_i.
+// (a1, A2: first and traceless-complete second moments of f^eq - f; BGK is
+// s_lo = s_hi.)  Each pair costs a handful of operations instead of
+// re-forming the equilibrium, the projection and the force term separately.
+template <typename R, bool G27, int Q>
+__device__ __forceinline__ void relax_pairs(R (&f)[Q], R shi, R e0, const Sym<R>& B, R Vx, R Vy,
+                                            R Vz) {
+  const R keep = R(1) - shi;
+  const R txy = R(2) * B.xy, txz = R(2) * B.xz, tyz = R(2) * B.yz;
+  {
+    // rest population: c = 0
+    f[0] = keep * f[0] + R(wdir<G27>(0)) * e0;
+  }
+#pragma unroll
+  for (int k = 1; k < Q; k += 2) {
+    const Dir d = cdir<G27>(k);
+    const R w = R(wdir<G27>(k));
+    const R ev = w * (e0 + R(4.5) * quad(d, B, txy, txz, tyz));
+    const R od = w * dot(d, Vx, Vy, Vz);
+    const R fi = f[k], fj = f[k + 1];
+    f[k] = keep * fi + (ev + od);
+    f[k + 1] = keep * fj + (ev - od);
+  }
+}
+
+// S12-S13: hydrodynamic collision in place.  Equilibrium g^eq = w [p* + 3 c.u
+// + 9/2 (c.u)^2 - 3/2 u.u]; moments of Delta = g^eq - g: a1 = u - j,
+// A2 = p/3 I + u u - Pi; Guo source 3 w c.F / rho applied with (1 - omega/2).
 template <typename R, bool MRT>
 __device__ __forceinline__ void collide_g(R (&g)[Q_G], const CellState<R>& c, const Phys<R>& P) {
   const R uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
   const R om = c.omega;
-  const R fk = (R(1) - R(0.5) * om) * R(3) / c.rho;   // (1 - om/2) 3 F / rho per w c.F
-  const R base = c.p - R(1.5) * uu;
   const R shi = MRT ? P.s_high : om;
   const R dlo = om - shi;
-  // moments of Delta = g^eq - g: a1 = u - j, A2 = p/3 I + u u - Pi
-  const R a1x = c.ux - c.jx, a1y = c.uy - c.jy, a1z = c.uz - c.jz;
-  const R p3 = c.p * (R(1) / R(3));
-  Sym<R> A2{p3 + c.ux * c.ux - c.Pi.xx, p3 + c.uy * c.uy - c.Pi.yy, p3 + c.uz * c.uz - c.Pi.zz,
-            c.ux * c.uy - c.Pi.xy, c.ux * c.uz - c.Pi.xz, c.uy * c.uz - c.Pi.yz};
-  {
-    const R w = R(wg(0));
-    R v = g[0] + shi * (w * base - g[0]);
-    if (MRT) v += dlo * w * R(4.5) * hermite2(cg(0), A2);
-    g[0] = v;
+  const R fk = (R(1) - R(0.5) * om) * R(3) / c.rho;   // Guo: (1 - om/2) 3 F / rho per w c.F
+  Sym<R> B{shi * c.ux * c.ux, shi * c.uy * c.uy, shi * c.uz * c.uz,
+           shi * c.ux * c.uy, shi * c.ux * c.uz, shi * c.uy * c.uz};
+  R e0 = shi * (c.p - R(1.5) * uu);
+  R Vx = R(3) * shi * c.ux + fk * c.Fx, Vy = R(3) * shi * c.uy + fk * c.Fy,
+    Vz = R(3) * shi * c.uz + fk * c.Fz;
+  if (MRT) {
+    const R p3 = c.p * (R(1) / R(3));
+    const Sym<R> A2{p3 + c.ux * c.ux - c.Pi.xx, p3 + c.uy * c.uy - c.Pi.yy, p3 + c.uz * c.uz - c.Pi.zz,
+                    c.ux * c.uy - c.Pi.xy, c.ux * c.uz - c.Pi.xz, c.uy * c.uz - c.Pi.yz};
+    B.xx += dlo * A2.xx; B.yy += dlo * A2.yy; B.zz += dlo * A2.zz;
+    B.xy += dlo * A2.xy; B.xz += dlo * A2.xz; B.yz += dlo * A2.yz;
+    e0 -= R(1.5) * dlo * (A2.xx + A2.yy + A2.zz);
+    const R d3 = R(3) * dlo;
+    Vx += d3 * (c.ux - c.jx);
+    Vy += d3 * (c.uy - c.jy);
+    Vz += d3 * (c.uz - c.jz);
   }
-#pragma unroll
-  for (int k = 1; k < Q_G; k += 2) {
-    const Dir d = cg(k);
-    const R w = R(wg(k));
-    const R cu = dot(d, c.ux, c.uy, c.uz);
-    const R ev = w * (base + R(4.5) * cu * cu);
-    const R od = w * R(3) * cu;
-    const R fo = w * fk * dot(d, c.Fx, c.Fy, c.Fz);
-    R pe = R(0), po = R(0);
-    if (MRT) {
-      pe = dlo * w * R(4.5) * hermite2(d, A2);
-      po = dlo * w * R(3) * dot(d, a1x, a1y, a1z);
-    }
-    const R gi = g[k], gj = g[k + 1];
-    g[k] = gi + shi * (ev + od - gi) + fo + pe + po;
-    g[k + 1] = gj + shi * (ev - od - gj) - fo + pe - po;
-  }
+  relax_pairs<R, true, Q_G>(g, shi, e0, B, Vx, Vy, Vz);
 }
 
 // S14-S15: phase-field collision in place on the deviations h' (needs u
-// from the hydro prologue), in the same pair form.  With the reference
-// subtracted, h^eq_i - w_i phi_ref = w_i [dphi + phi (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)]
-// and the second moment of h' is that of h minus phi_ref I/3.
+// from the hydro prologue).  With the reference subtracted,
+// h^eq_i - w_i phi_ref = w_i [dphi + phi (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)], the
+// moments of Delta are a1 = phi u - j and A2 = dphi/3 I + phi u u - Pi' (Pi'
+// the second moment of h'), and the counter-term source w_i theta c.n is
+// applied with (1 - omega_phi/2).
 template <typename R, bool MRT>
 __device__ __forceinline__ void collide_h(R (&h)[Q_H], const CellState<R>& c, const Phys<R>& P) {
   const R uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
   const R om = P.omega_phi;
-  const R fk = (R(1) - R(0.5) * om) * c.theta;
   const R shi = MRT ? P.s_high : om;
   const R dlo = om - shi;
+  const R fk = (R(1) - R(0.5) * om) * c.theta;
   const R phi = c.phi;
-  Sym<R> A2{R(0), R(0), R(0), R(0), R(0), R(0)};
-  R a1x = R(0), a1y = R(0), a1z = R(0);
+  const R sp = shi * phi;
+  Sym<R> B{sp * c.ux * c.ux, sp * c.uy * c.uy, sp * c.uz * c.uz,
+           sp * c.ux * c.uy, sp * c.ux * c.uz, sp * c.uy * c.uz};
+  R e0 = shi * (c.dphi - R(1.5) * phi * uu);
+  R Vx = R(3) * sp * c.ux + fk * c.nx, Vy = R(3) * sp * c.uy + fk * c.ny,
+    Vz = R(3) * sp * c.uz + fk * c.nz;
   if (MRT) {
     R jx, jy, jz;
     Sym<R> Pi;
     pair_moments<R, false, Q_H>(h, jx, jy, jz, Pi);
-    // moments of h^eq - w phi_ref: phi u, dphi I/3 + phi u u
-    a1x = phi * c.ux - jx;
-    a1y = phi * c.uy - jy;
-    a1z = phi * c.uz - jz;
     const R p3 = c.dphi * (R(1) / R(3));
-    A2 = Sym<R>{p3 + phi * c.ux * c.ux - Pi.xx, p3 + phi * c.uy * c.uy - Pi.yy,
-                p3 + phi * c.uz * c.uz - Pi.zz, phi * c.ux * c.uy - Pi.xy,
-                phi * c.ux * c.uz - Pi.xz, phi * c.uy * c.uz - Pi.yz};
+    const Sym<R> A2{p3 + phi * c.ux * c.ux - Pi.xx, p3 + phi * c.uy * c.uy - Pi.yy,
+                    p3 + phi * c.uz * c.uz - Pi.zz, phi * c.ux * c.uy - Pi.xy,
+                    phi * c.ux * c.uz - Pi.xz, phi * c.uy * c.uz - Pi.yz};
+    B.xx += dlo * A2.xx; B.yy += dlo * A2.yy; B.zz += dlo * A2.zz;
+    B.xy += dlo * A2.xy; B.xz += dlo * A2.xz; B.yz += dlo * A2.yz;
+    e0 -= R(1.5) * dlo * (A2.xx + A2.yy + A2.zz);
+    const R d3 = R(3) * dlo;
+    Vx += d3 * (phi * c.ux - jx);
+    Vy += d3 * (phi * c.uy - jy);
+    Vz += d3 * (phi * c.uz - jz);
   }
-  const R base = c.dphi - R(1.5) * phi * uu;
-  {
-    const R w = R(wh(0));
-    R v = h[0] + shi * (w * base - h[0]);
-    if (MRT) v += dlo * w * R(4.5) * hermite2(ch(0), A2);
-    h[0] = v;
-  }
-#pragma unroll
-  for (int k = 1; k < Q_H; k += 2) {
-    const Dir d = ch(k);
-    const R w = R(wh(k));
-    const R cu = dot(d, c.ux, c.uy, c.uz);
-    const R ev = w * (base + R(4.5) * phi * cu * cu);
-    const R od = w * R(3) * phi * cu;
-    const R fo = w * fk * dot(d, c.nx, c.ny, c.nz);
-    R pe = R(0), po = R(0);
-    if (MRT) {
-      pe = dlo * w * R(4.5) * hermite2(d, A2);
-      po = dlo * w * R(3) * dot(d, a1x, a1y, a1z);
-    }
-    const R hi = h[k], hj = h[k + 1];
-    h[k] = hi + shi * (ev + od - hi) + fo + pe + po;
-    h[k + 1] = hj + shi * (ev - od - hj) - fo + pe - po;
-  }
+  relax_pairs<R, false, Q_H>(h, shi, e0, B, Vx, Vy, Vz);
 }
 
 }  // namespace pflbm
