@@ -27,6 +27,11 @@
 
 namespace pflbm {
 
+// the four stencil adjoints of one cell, stored together (one 16- or 32-byte
+// access per cell)
+template <typename R>
+struct alignas(4 * sizeof(R)) S4 { R gx, gy, gz, l; };
+
 template <typename R>
 struct AdjConst {
   R beta4_per_sigma;   // 48 / xi  (0 if xi = inf)
@@ -351,7 +356,7 @@ struct AdjArgs {
   const R* aphi_in;
   R* lh_out;
   R* lg_out;
-  R* sadj;          // [4][N]: dL/d(grad phi x, y, z), dL/d(lap phi)
+  S4<R>* sadj;      // [N]: dL/d(grad phi x, y, z), dL/d(lap phi)
   double* gsum;     // [nblocks][2] running sums of dL/domega_phi, dL/dsigma
   Geom geo;
   Phys<R> P;
@@ -423,10 +428,7 @@ void k_adj_cell(AdjArgs<S> a) {
     for (int i = 0; i < Q_H; ++i) *slot(a.lh_out, G.N, i, idx) = lh[i];
 #pragma unroll
     for (int i = 0; i < Q_G; ++i) *slot(a.lg_out, G.N, i, idx) = lg[i];
-    *slot(a.sadj, G.N, 0, idx) = lGx;
-    *slot(a.sadj, G.N, 1, idx) = lGy;
-    *slot(a.sadj, G.N, 2, idx) = lGz;
-    *slot(a.sadj, G.N, 3, idx) = lL;
+    a.sadj[idx] = S4<R>{lGx, lGy, lGz, lL};
     acc0 = double(lomp);
     acc1 = double(lsig);
   }
@@ -450,8 +452,8 @@ void k_adj_cell(AdjArgs<S> a) {
 
 template <typename R>
 struct AdjStencilArgs {
-  const R* sadj;      // [4][N]
-  const unsigned char* mask;
+  const S4<R>* sadj;  // [N]
+  const unsigned* nbr; // solid-neighbour bits (mask only)
   R* aphi_out;        // [N]
   Geom geo;
 };
@@ -459,14 +461,15 @@ struct AdjStencilArgs {
 // a_phi(y) = sum_m valid(y, m) [-3 w_m c_m.(s_G(y+c_m) + s_G(y)) + 6 w_m (s_L(y+c_m) - s_L(y))]
 // Marching in z like the forward step: each block owns a tile and a chunk of
 // planes and keeps the stencil adjoints of 4 planes (tile + one-cell ring) in
-// an LDS ring, so every value is read from memory about once.
+// an LDS ring, so every value is read from memory about once; the loads of
+// plane z + 2 are in flight while plane z is summed.  valid(y, m) is the
+// cell's wall bits (box faces and solid neighbours), as in the forward step.
 template <typename R, bool MASK>
 __global__ __launch_bounds__(256) void k_adj_stencil(AdjStencilArgs<R> a) {
   extern __shared__ unsigned char smem_raw[];
   const Geom& G = a.geo;
   const int TX = G.bx + 2, TY = G.by + 2, TXY = TX * TY;
-  R* ts = reinterpret_cast<R*>(smem_raw);                                // [4 slots][4][TXY]
-  unsigned char* tv = reinterpret_cast<unsigned char*>(ts + 16 * TXY);   // [4 slots][TXY] validity
+  S4<R>* ts = reinterpret_cast<S4<R>*>(smem_raw);                        // [4 slots][TXY]
   const ChunkCoord t = chunk_of_block(G);
   const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + ly * G.bx;
   const int x = t.x0 + lx, y = t.y0 + ly;
@@ -489,55 +492,58 @@ __global__ __launch_bounds__(256) void k_adj_stencil(AdjStencilArgs<R> a) {
     halo_ok = wrap(hx, G.nx, G.px) && wrap(hy, G.ny, G.py);
   }
   const unsigned sxy = (unsigned)G.nx * (unsigned)G.ny;
-  auto fill = [&](int slotk, int pos, bool ok, int X, int Y, int Z) {
-    R v0 = R(0), v1 = R(0), v2 = R(0), v3 = R(0);
-    unsigned char valid = 0;
-    if (ok) {
-      const unsigned id = X + G.nx * Y + sxy * Z;
-      if (!MASK || !a.mask[id]) {
-        valid = 1;
-        v0 = *slot(a.sadj, G.N, 0, id);
-        v1 = *slot(a.sadj, G.N, 1, id);
-        v2 = *slot(a.sadj, G.N, 2, id);
-        v3 = *slot(a.sadj, G.N, 3, id);
-      }
-    }
-    R* b = ts + slotk * 4 * TXY;
-    b[pos] = v0;
-    b[TXY + pos] = v1;
-    b[2 * TXY + pos] = v2;
-    b[3 * TXY + pos] = v3;
-    tv[slotk * TXY + pos] = valid;
+  // stencil adjoints of solid or out-of-box positions are never used (the
+  // wall bits exclude them), so they are simply not loaded
+  auto fetch = [&](bool ok, int X, int Y, int Z) {
+    S4<R> c{R(0), R(0), R(0), R(0)};
+    if (ok) c = a.sadj[X + G.nx * Y + sxy * Z];
+    return c;
   };
-  auto plane = [&](int p) {
+  S4<R> own{R(0), R(0), R(0), R(0)}, ring{R(0), R(0), R(0), R(0)};
+  auto fetch_plane = [&](int p) {
     int pz = p;
     const bool zok = wrap(pz, G.nz, G.pz);
-    fill(p & 3, opos, own_ok && zok, ox, oy, pz);
-    if (tid < NH) fill(p & 3, hpos, halo_ok && zok, hx, hy, pz);
+    own = fetch(own_ok && zok, ox, oy, pz);
+    if (tid < NH) ring = fetch(halo_ok && zok, hx, hy, pz);
   };
-  plane(t.z0 - 1);
-  plane(t.z0);
+  auto put_plane = [&](int p) {
+    ts[(p & 3) * TXY + opos] = own;
+    if (tid < NH) ts[(p & 3) * TXY + hpos] = ring;
+  };
+  fetch_plane(t.z0 - 1);
+  put_plane(t.z0 - 1);
+  fetch_plane(t.z0);
+  put_plane(t.z0);
+  fetch_plane(t.z0 + 1);
   for (int z = t.z0; z < t.z1; ++z) {
-    plane(z + 1);
+    // plane z + 1 (fetched one iteration ago) into the ring, then start the
+    // loads of plane z + 2 so they overlap this plane's arithmetic
+    put_plane(z + 1);
+    if (z + 1 < t.z1) fetch_plane(z + 2);
     __syncthreads();
-    const int sm = (z - 1) & 3, s0 = z & 3, sp = (z + 1) & 3;
-    if (active && tv[s0 * TXY + opos]) {
-      const R* c0 = ts + s0 * 4 * TXY;
-      const R sx = c0[opos], sy = c0[TXY + opos], sz = c0[2 * TXY + opos], sl = c0[3 * TXY + opos];
-      R acc = R(0);
+    if (active) {
+      const unsigned idx = x + G.nx * y + sxy * z;
+      bool solid;
+      const unsigned walls = cell_walls<MASK>(x, y, z, idx, G, a.nbr, solid);
+      if (!solid) {
+        const S4<R>* pm = ts + ((z - 1) & 3) * TXY;
+        const S4<R>* p0 = ts + (z & 3) * TXY;
+        const S4<R>* pp = ts + ((z + 1) & 3) * TXY;
+        const S4<R> c0 = p0[opos];
+        R acc = R(0);
 #pragma unroll
-      for (int k = 1; k < 27; ++k) {
-        const Dir d = cg(k);
-        const int sk = d.z < 0 ? sm : (d.z > 0 ? sp : s0);
-        const int e = (ly + 1 + d.y) * TX + (lx + 1 + d.x);
-        if (tv[sk * TXY + e]) {
-          const R* b = ts + sk * 4 * TXY;
-          const R w = R(wg(k));
-          const R gsum = dot(d, b[e] + sx, b[TXY + e] + sy, b[2 * TXY + e] + sz);
-          acc += R(-3) * w * gsum + R(6) * w * (b[3 * TXY + e] - sl);
+        for (int k = 1; k < 27; ++k) {
+          if (!(walls & (1u << k))) {
+            const Dir d = cg(k);
+            const S4<R>* pl = d.z < 0 ? pm : (d.z > 0 ? pp : p0);
+            const S4<R> m = pl[(ly + 1 + d.y) * TX + (lx + 1 + d.x)];
+            const R w = R(wg(k));
+            const R gsum = dot(d, m.gx + c0.gx, m.gy + c0.gy, m.gz + c0.gz);
+            acc += R(-3) * w * gsum + R(6) * w * (m.l - c0.l);
+          }
         }
+        a.aphi_out[idx] = acc;
       }
-      a.aphi_out[x + G.nx * y + sxy * z] = acc;
     }
   }
 }
