@@ -164,6 +164,43 @@ def precision_errors(wl, checkpoints=(100, 500, 1000)):
     return out
 
 
+def long_run(wl, steps=20000, every=5000):
+    """The workload's full run in FP32 against FP64: max|dphi|, mass drift and
+    the rise of the light phase's centroid (sum (1 - phi) y / sum (1 - phi))."""
+    import torch
+
+    from paper_2206_11637_amd.sim import from_workload
+    y = torch.arange(wl.ny, dtype=torch.float64, device="cuda").view(1, wl.ny, 1) + 0.5
+
+    def centroid(phi):
+        light = 1.0 - phi
+        return float((light * y).sum() / light.sum())
+
+    out, ref = {}, {}
+    for prec in ("fp64", "fp32"):
+        sim = from_workload(wl, precision=prec)
+        m0 = sim.reduce()[0]
+        c0 = centroid(sim.phi())
+        n = 0
+        for k in range(every, steps + 1, every):
+            sim.step(k - n)
+            n = k
+            phi = sim.phi()
+            rec = {"light_centroid_rise": centroid(phi) - c0,
+                   "mass_drift": (sim.reduce()[0] - m0) / m0}
+            if prec == "fp64":
+                ref[k] = phi
+            else:
+                rec["max_abs_dphi_vs_fp64"] = (phi - ref[k]).abs().max().item()
+            out[f"{prec}_step{k}"] = rec
+            del phi
+        del sim
+        torch.cuda.empty_cache()
+    del ref
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline():
     """The FP64 oracle on a bounded sample of the same workload (a z-slab of
     the rising-bubble lattice with its walls), timed on the host cores."""
@@ -244,6 +281,7 @@ def main():
     if not args.no_forms:
         half = max(args.steps // 2, 10)
         form("fp64_rising_bubble_128x512x128", time_form, wl1, "fp64", half, args.warmup)
+        form("rising_bubble_20k_steps_fp32_vs_fp64", long_run, wl1)
         # the in-place AA scheme: half the population memory, a separate phi pass
         form("fp32_in_place_aa_rising_bubble_128x512x128", time_form, wl1, "fp32", half, args.warmup,
              "mrt", "aa")
