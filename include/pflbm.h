@@ -105,6 +105,12 @@ typedef struct {
                              |k| <= 24); ignored by the other precisions          */
   double normal_eps;      /* > 0: n = grad phi / sqrt(|grad phi|^2 + eps^2); 1e-4 is
                              the reference choice (see the design notes)          */
+  double s_bulk;          /* MRT rate of the bulk mode of g (the trace of its
+                             second-order moments, polynomial |c|^2 - 1): 0 = the
+                             second-order rate omega(phi) (default), else in (0, 2).
+                             The viscous force F_mu then recovers the trace part of
+                             the strain rate with this rate.  Ignored by BGK; the
+                             adjoint entry points accept only 0                   */
 } pflbm_params;
 
 /* Bytes of device workspace for a context with this description (256-aligned
@@ -124,7 +130,8 @@ pflbm_status pflbm_create(const pflbm_desc* desc, void* d_workspace, size_t byte
 pflbm_status pflbm_destroy(pflbm_ctx* ctx);
 
 /* Validates and sets the physical parameters (tau > 1/2, M > 0, xi > 0,
- * sigma >= 0, rho > 0, 0 < s_high < 2, normal_eps > 0).  Takes effect for the
+ * sigma >= 0, rho > 0, 0 < s_high < 2, normal_eps > 0, s_bulk = 0 or in
+ * (0, 2)).  Takes effect for the
  * next step. */
 pflbm_status pflbm_set_params(pflbm_ctx* ctx, const pflbm_params* params);
 
@@ -239,7 +246,8 @@ pflbm_status pflbm_adjoint_inject_phi(pflbm_ctx* ctx, const double* d_dl_dphi);
 /* One reverse step: lambda^{n+1} -> lambda^n through the step n -> n+1,
  * using the primal state of level n (a buffer written by pflbm_save_state
  * when the step count was n, or by pflbm_step_states with its phi^n formed),
- * and adds this step's contributions to dL/dM and dL/dsigma. */
+ * and adds this step's contributions to dL/dM and dL/dsigma.  Returns
+ * PFLBM_ERR_UNSUPPORTED for an MRT context whose s_bulk is not 0. */
 pflbm_status pflbm_adjoint_step(pflbm_ctx* ctx, const void* d_state_n, int64_t n);
 
 /* Reverse of pflbm_init_equilibrium for phi0: d_dphi0 [N] (FP64) receives

@@ -30,6 +30,10 @@ One step n -> n+1 (paper sec. "Conservative Allen-Cahn model"):
   S9  u' = j + (F_s + F_b + F_p) / (2 rho)
   S10 Pi_neq = sum_i c_i c_i^T (g_i - g_i^eq(p*, u')),
       F_mu = -(1 - omega/2)(rho_H - rho_L) Pi_neq grad phi
+      (with a separate bulk rate s_b, MRT only: the trace part of Pi_neq is
+      scaled by s_b/omega, so that the force still equals
+      nu (rho_H - rho_L)(grad u + grad u^T) grad phi when the trace of the
+      strain rate is read from a mode relaxed at s_b)
       (the viscous force from non-equilibrium moments instead of finite
       differences of u, as the paper remarks at the end of the LBE section)
   S11 F = F_s + F_b + F_p + F_mu ; u = j + F / (2 rho)
@@ -46,7 +50,10 @@ Relaxation rates (one rate per polynomial degree of the moment basis):
   h: degrees 1 and 2 relax with omega_phi = 1/(3M + 1/2) (tau_phi = M/c_s^2 is
      the relaxation time measured from the half-step, eq. pflbm-tau), degrees
      >= 3 with s_high.
-  g: degrees <= 2 relax with omega(phi), degrees >= 3 with s_high.
+  g: degrees <= 2 relax with omega(phi), degrees >= 3 with s_high; optionally
+     (s_bulk > 0) the bulk mode w_i (|c_i|^2 - 1), the trace of the degree-2
+     moments, relaxes with s_bulk instead (a reading: the paper relaxes the
+     moments after a reference it does not restate; see bulk_part).
   BGK: every degree relaxes with omega_phi (h) or omega(phi) (g) (eq. BGK).
 """
 from __future__ import annotations
@@ -77,11 +84,13 @@ class OracleParams:
     s_high: float = 1.0
     collision: str = "mrt"  # "mrt" or "bgk"
     eps_normal: float = 1e-4
+    s_bulk: float = 0.0     # 0: the bulk mode of g relaxes with omega(phi)
 
     @classmethod
     def from_workload(cls, p, collision="mrt") -> "OracleParams":
         return cls(p.tau_H, p.tau_L, p.mobility, p.xi, p.sigma, p.rho_H, p.rho_L,
-                   tuple(p.g), p.s_high, collision, p.normal_eps)
+                   tuple(p.g), p.s_high, collision, p.normal_eps,
+                   float(getattr(p, "s_bulk", 0.0)))
 
 
 class Grid:
@@ -146,6 +155,19 @@ def mrt_apply(lat: Lattice, rates: torch.Tensor, vec: torch.Tensor) -> torch.Ten
     return lat.Minv @ (rates * (lat.M @ vec))
 
 
+def bulk_part(lat: Lattice, vec: torch.Tensor) -> torch.Tensor:
+    """Component of vec [q, N] along the bulk mode.
+
+    The polynomial b(c) = |c|^2 - 1 = 3 (|c|^2 - c_s^2) lies in the degree-2
+    space of the weighted-orthogonal basis (it is orthogonal to 1 and to c
+    under <p, q> = sum_i w_i p(c_i) q(c_i)) and is orthogonal to its traceless
+    members, so a distribution splits into w_i b(c_i) m_b / <b, b> plus parts
+    the other rates act on, with m_b = sum_i b(c_i) vec_i."""
+    b = (lat.c * lat.c).sum(1) - 1.0
+    norm = (lat.w * b * b).sum()
+    return (lat.w * b)[:, None] * ((b[:, None] * vec).sum(0) / norm)[None, :]
+
+
 def _rates(lat: Lattice, low: torch.Tensor, s_high, bgk: bool, n: int) -> torch.Tensor:
     """Per-moment, per-cell rate: degree <= 2 -> low, degree >= 3 -> s_high (or low if BGK)."""
     low = low.reshape(1, -1).expand(lat.q, n) if low.dim() > 0 else low.reshape(1, 1).expand(lat.q, n)
@@ -202,6 +224,11 @@ def collide(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
     geq1 = equilibrium(LG, pstar, u1, False)
     neq = g - geq1
     Pi = torch.einsum("ia,ib,in->abn", LG.c, LG.c, neq)
+    bulk = (not bgk) and prm.s_bulk > 0
+    if bulk:
+        tr = (Pi[0, 0] + Pi[1, 1] + Pi[2, 2]) / 3.0
+        Pi = Pi + (prm.s_bulk * tau - 1.0)[None, None, :] * tr[None, None, :] \
+            * torch.eye(3, dtype=F64)[:, :, None]
     Fmu = -((1.0 - 0.5 * omega) * drho)[None, :] * torch.einsum("abn,bn->an", Pi, grad)
     # S11
     F = Fs + Fb + Fp + Fmu
@@ -211,6 +238,8 @@ def collide(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
     Fg = 3.0 * LG.w[:, None] * (LG.c @ F) / rho[None, :]
     sg = _rates(LG, omega, prm.s_high, bgk, N)
     gstar = g + mrt_apply(LG, sg, geq - g) + mrt_apply(LG, 1.0 - 0.5 * sg, Fg)
+    if bulk:   # the source 3 w c.F / rho is odd in c: no bulk component
+        gstar = gstar + (prm.s_bulk - omega)[None, :] * bulk_part(LG, geq - g)
     # S14, S15
     heq = equilibrium(LH, phi, u, True)
     Fh = LH.w[:, None] * theta[None, :] * (LH.c @ normal)

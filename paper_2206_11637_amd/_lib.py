@@ -24,7 +24,8 @@ class Params(C.Structure):
     _fields_ = [("tau_H", C.c_double), ("tau_L", C.c_double), ("mobility", C.c_double),
                 ("xi", C.c_double), ("sigma", C.c_double), ("rho_H", C.c_double),
                 ("rho_L", C.c_double), ("g", C.c_double * 3), ("s_high", C.c_double),
-                ("fp16_scale_log2", C.c_double * 2), ("normal_eps", C.c_double)]
+                ("fp16_scale_log2", C.c_double * 2), ("normal_eps", C.c_double),
+                ("s_bulk", C.c_double)]
 
 
 # name: (restype, argtypes)

@@ -33,6 +33,7 @@ struct Phys {
   R omega_phi;        // 1 / (3 M + 1/2)
   R s_high;           // rate of degree >= 3 moments (MRT)
   R eps2;             // eps^2: n = grad phi / sqrt(|grad phi|^2 + eps^2)
+  R s_bulk;           // rate of the bulk mode of g (MRT); 0: the second-order rate
 };
 
 // second-moment tensor of a population set, symmetric storage xx yy zz xy xz yz
@@ -101,7 +102,8 @@ __device__ __forceinline__ void prologue(R phi, R dphi, const R (&g)[Q_G], R Gx,
   c.phi = phi;
   c.dphi = dphi;
   c.rho = P.rho_L + phi * P.drho;
-  c.omega = R(1) / (P.tau_L + phi * P.dtau);
+  const R tau = P.tau_L + phi * P.dtau;
+  c.omega = R(1) / tau;
   c.theta = P.theta_k * phi * (R(1) - phi);
   const R ninv = R(1) / sqrt(Gx * Gx + Gy * Gy + Gz * Gz + P.eps2);
   c.nx = Gx * ninv;
@@ -139,9 +141,13 @@ __device__ __forceinline__ void prologue(R phi, R dphi, const R (&g)[Q_G], R Gx,
   const R nxz = Pi.xz - u1x * u1z;
   const R nyz = Pi.yz - u1y * u1z;
   const R fmu = -(R(1) - R(0.5) * c.omega) * P.drho;
-  c.Fx = F0x + fmu * (nxx * Gx + nxy * Gy + nxz * Gz);
-  c.Fy = F0y + fmu * (nxy * Gx + nyy * Gy + nyz * Gz);
-  c.Fz = F0z + fmu * (nxz * Gx + nyz * Gy + nzz * Gz);
+  // with the bulk mode relaxed at s_bulk its non-equilibrium part carries the
+  // trace of the strain rate scaled by 1/s_bulk instead of 1/omega
+  const R kb = P.s_bulk > R(0) ? P.s_bulk * tau - R(1) : R(0);
+  const R tb = kb * (nxx + nyy + nzz) * (R(1) / R(3));
+  c.Fx = F0x + fmu * ((nxx + tb) * Gx + nxy * Gy + nxz * Gz);
+  c.Fy = F0y + fmu * (nxy * Gx + (nyy + tb) * Gy + nyz * Gz);
+  c.Fz = F0z + fmu * (nxz * Gx + nyz * Gy + (nzz + tb) * Gz);
   c.ux = jx + c.Fx * inv2rho;
   c.uy = jy + c.Fy * inv2rho;
   c.uz = jz + c.Fz * inv2rho;
@@ -218,6 +224,7 @@ __device__ __forceinline__ void relax_pairs(R (&f)[Q], R shi, R e0, const Sym<R>
 // S12-S13: hydrodynamic collision in place.  Equilibrium g^eq = w [p* + 3 c.u
 // + 9/2 (c.u)^2 - 3/2 u.u]; moments of Delta = g^eq - g: a1 = u - j,
 // A2 = p/3 I + u u - Pi; Guo source 3 w c.F / rho applied with (1 - omega/2).
+// With s_bulk set, the trace part of the second-order relaxation uses it.
 template <typename R, bool MRT>
 __device__ __forceinline__ void collide_g(R (&g)[Q_G], const CellState<R>& c, const Phys<R>& P) {
   const R uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
@@ -234,9 +241,12 @@ __device__ __forceinline__ void collide_g(R (&g)[Q_G], const CellState<R>& c, co
     const R p3 = c.p * (R(1) / R(3));
     const Sym<R> A2{p3 + c.ux * c.ux - c.Pi.xx, p3 + c.uy * c.uy - c.Pi.yy, p3 + c.uz * c.uz - c.Pi.zz,
                     c.ux * c.uy - c.Pi.xy, c.ux * c.uz - c.Pi.xz, c.uy * c.uz - c.Pi.yz};
-    B.xx += dlo * A2.xx; B.yy += dlo * A2.yy; B.zz += dlo * A2.zz;
+    // the bulk mode w (|c|^2 - 1) tr(A2)/3 relaxes at s_bulk instead of omega
+    const R trA2 = A2.xx + A2.yy + A2.zz;
+    const R db = P.s_bulk > R(0) ? (P.s_bulk - om) * trA2 * (R(1) / R(3)) : R(0);
+    B.xx += dlo * A2.xx + db; B.yy += dlo * A2.yy + db; B.zz += dlo * A2.zz + db;
     B.xy += dlo * A2.xy; B.xz += dlo * A2.xz; B.yz += dlo * A2.yz;
-    e0 -= R(1.5) * dlo * (A2.xx + A2.yy + A2.zz);
+    e0 -= R(1.5) * dlo * trA2 + R(4.5) * db;
     const R d3 = R(3) * dlo;
     Vx += d3 * (c.ux - c.jx);
     Vy += d3 * (c.uy - c.jy);

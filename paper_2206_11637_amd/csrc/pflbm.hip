@@ -173,7 +173,7 @@ Geom make_geom(const pflbm_ctx* c) {
 }
 
 template <typename R>
-Phys<R> make_phys(const pflbm_params& p) {
+Phys<R> make_phys(const pflbm_params& p, int32_t collision) {
   Phys<R> P;
   const bool inf_xi = std::isinf(p.xi);
   P.tau_L = R(p.tau_L);
@@ -187,6 +187,7 @@ Phys<R> make_phys(const pflbm_params& p) {
   P.omega_phi = R(1.0 / (3.0 * p.mobility + 0.5));
   P.s_high = R(p.s_high);
   P.eps2 = R(p.normal_eps * p.normal_eps);
+  P.s_bulk = collision == PFLBM_MRT ? R(p.s_bulk) : R(0);
   return P;
 }
 
@@ -248,7 +249,7 @@ StepArgs<S> step_args(pflbm_ctx* c) {
   a.phi_src_out = nullptr;
   a.nbr = nbr_ptr(c);
   a.geo = make_geom(c);
-  a.P = make_phys<R>(c->p);
+  a.P = make_phys<R>(c->p, c->d.collision);
   a.cd = make_codec<R>(c);
   return a;
 }
@@ -336,7 +337,7 @@ CellArgs<S> aa_args(pflbm_ctx* c) {
   a.phi_prev = phi_prev<R>(c);
   a.mask = mask_ptr(c);
   a.geo = make_geom(c);
-  a.P = make_phys<R>(c->p);
+  a.P = make_phys<R>(c->p, c->d.collision);
   a.cd = make_codec<R>(c);
   a.out_phi = a.out_u = a.out_p = nullptr;
   return a;
@@ -627,6 +628,8 @@ pflbm_status params_ok(const pflbm_params* p, std::string& why) {
   if (bad(!(p->s_high > 0 && p->s_high < 2), "s_high must lie in (0, 2)")) return PFLBM_ERR_ARG;
   if (bad(!(p->normal_eps > 0) || !std::isfinite(p->normal_eps), "normal_eps must be > 0"))
     return PFLBM_ERR_ARG;
+  if (bad(!(p->s_bulk == 0 || (p->s_bulk > 0 && p->s_bulk < 2)), "s_bulk must be 0 or lie in (0, 2)"))
+    return PFLBM_ERR_ARG;
   for (int k = 0; k < 3; ++k)
     if (bad(!std::isfinite(p->g[k]), "g must be finite")) return PFLBM_ERR_ARG;
   for (int k = 0; k < 2; ++k) {
@@ -671,6 +674,7 @@ pflbm_status pflbm_create(const pflbm_desc* desc, void* d_workspace, size_t byte
   p.fp16_scale_log2[0] = 12;
   p.fp16_scale_log2[1] = 12;
   p.normal_eps = 1e-4;
+  p.s_bulk = 0.0;
   c->p = p;
   *out = c;
   return PFLBM_OK;

@@ -37,6 +37,7 @@ def _params_struct(p) -> Params:
     for k, v in enumerate(get("fp16_scale_log2")):
         s.fp16_scale_log2[k] = v
     s.normal_eps = get("normal_eps")
+    s.s_bulk = (p.get("s_bulk", 0.0) if isinstance(p, dict) else getattr(p, "s_bulk", 0.0))
     return s
 
 

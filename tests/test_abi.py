@@ -72,11 +72,14 @@ def test_parameter_validation_without_a_gpu():
     good = _params_struct(W.Params())
     assert lib.pflbm_set_params(ctx, C.byref(good)) == 0
     for field, val in (("tau_H", 0.5), ("mobility", 0.0), ("xi", -1.0), ("sigma", -1e-4),
-                       ("rho_L", 0.0), ("s_high", 2.0)):
+                       ("rho_L", 0.0), ("s_high", 2.0), ("s_bulk", 2.0), ("s_bulk", -0.5)):
         p = _params_struct(W.Params())
         setattr(p, field, val)
         assert lib.pflbm_set_params(ctx, C.byref(p)) == L.PFLBM_ERR_ARG, field
         assert len(lib.pflbm_last_error(ctx)) > 0
+    for sb in (0.0, 1.0, 1.99):
+        p = _params_struct(W.Params(s_bulk=sb))
+        assert lib.pflbm_set_params(ctx, C.byref(p)) == 0, sb
     p = _params_struct(W.Params())
     p.fp16_scale_log2[0] = 3.5
     assert lib.pflbm_set_params(ctx, C.byref(p)) == L.PFLBM_ERR_ARG

@@ -194,3 +194,24 @@ def test_in_place_scheme_gives_the_same_gradients(precision, tol):
     e_phi = (pa - pb).abs().max().item() / pa.abs().max().item()
     say(f"  L {_rel(Lb, La):.1e} dM {_rel(Mb, Ma):.1e} dsigma {_rel(sb, sa):.1e} dphi0 {e_phi:.1e}")
     assert _rel(Lb, La) <= tol and _rel(Mb, Ma) <= tol and _rel(sb, sa) <= tol and e_phi <= tol
+
+
+def test_reverse_mode_refuses_a_bulk_rate():
+    """The hand-written reverse step is derived with the bulk mode relaxed at
+    omega(phi): an MRT context with s_bulk set is refused, not differentiated
+    wrongly; BGK (which ignores s_bulk) is accepted."""
+    from paper_2206_11637_amd._lib import PFLBMError
+    from paper_2206_11637_amd.sim import from_workload
+    wl = _small("mrt", False)
+    wl = dataclasses.replace(wl, params=wl.params.copy(s_bulk=1.0))
+    say("case: adjoint with s_bulk = 1 (mrt refused, bgk accepted)")
+    for collision in ("mrt", "bgk"):
+        sim = from_workload(wl, precision="fp64", collision=collision)
+        state = sim.save_state()
+        sim.adjoint_attach()
+        if collision == "mrt":
+            with pytest.raises(PFLBMError, match="s_bulk"):
+                sim.adjoint_step(state, 0)
+        else:
+            sim.adjoint_step(state, 0)
+            sim.sync()

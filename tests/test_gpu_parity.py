@@ -1,4 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -75,6 +77,59 @@ def test_ragged_grids_walls_and_solids_match_oracle(case, collision, streaming):
     sim.step(steps)
     assert sim.step_count == steps
     _compare_fields(sim, grid, prm, h, g, TOL64, f"after {steps}")
+
+
+@pytest.mark.parametrize("streaming", STREAMING)
+@pytest.mark.parametrize("s_bulk,tau_L,rho_L", [(1.0, 0.512, 1.0 / 744.0), (1.6, 0.6, 0.05)])
+def test_bulk_mode_rate_matches_oracle(s_bulk, tau_L, rho_L, streaming):
+    """MRT with the bulk mode of g relaxed at its own rate: FP64 parity on a
+    walled ragged grid with solids, at the Taylor-bubble density ratio 744 and
+    gas relaxation time (bulk rate 1) and on a milder case (bulk rate 1.6; at
+    the Taylor values that rate lets the random start diverge), and BGK
+    ignoring the rate (identical to s_bulk = 0)."""
+    p = W.Params(tau_H=0.568, tau_L=tau_L, mobility=0.08, xi=3.0, sigma=6.6e-4,
+                 rho_L=rho_L, g=(0.0, -1.6e-5, 0.0), s_bulk=s_bulk)
+    wl = W.random_state(37, 19, 6, periodic=(False, False, False), params=p,
+                        solid_fraction=0.1, seed=41, steps=9)
+    say(f"case: bulk rate {s_bulk} {streaming}")
+    grid, prm, h, g = oracle_setup(wl, "mrt")
+    assert prm.s_bulk == s_bulk
+    sim = _sim(wl, "fp64", "mrt", streaming)
+    h, g = OP.run(grid, prm, h, g, wl.steps)
+    sim.step(wl.steps)
+    _compare_fields(sim, grid, prm, h, g, TOL64, f"bulk {s_bulk} after {wl.steps}")
+    # the rate changes the result ... (fluid cells: solid slots are never written)
+    fl = torch.as_tensor(~wl.solid.reshape(-1), device=sim.device)
+    wl0 = dataclasses.replace(wl, params=p.copy(s_bulk=0.0))
+    sim0 = _sim(wl0, "fp64", "mrt", streaming)
+    sim0.step(wl.steps)
+    d = (sim0.populations()[1][:, fl] - sim.populations()[1][:, fl]).abs().max().item()
+    assert d > 1e-9, d
+    # ... except under BGK, where every moment shares omega(phi) (milder
+    # parameters: BGK itself diverges at these within a few steps)
+    mild = p.copy(tau_L=0.7, rho_L=0.05)
+    a = _sim(dataclasses.replace(wl, params=mild), "fp64", "bgk", streaming)
+    b = _sim(dataclasses.replace(wl, params=mild.copy(s_bulk=0.0)), "fp64", "bgk", streaming)
+    a.step(wl.steps)
+    b.step(wl.steps)
+    ga, gb = a.populations()[1][:, fl], b.populations()[1][:, fl]
+    assert bool(torch.isfinite(ga).all()) and torch.equal(ga, gb)
+
+
+@pytest.mark.parametrize("precision,tol_phi", [("fp32", 1e-6), ("fp16s", 2e-4)])
+def test_bulk_mode_rate_in_reduced_precision(precision, tol_phi):
+    """The bulk rate in the FP32 forms against the FP64 path (capillary wave,
+    200 steps, s_bulk = 1)."""
+    wl = W.config0()
+    wl = dataclasses.replace(wl, params=wl.params.copy(s_bulk=1.0))
+    say(f"case: config0 s_bulk=1 {precision} vs fp64")
+    ref = _sim(wl, "fp64")
+    ref.step(wl.steps)
+    sim = _sim(wl, precision)
+    sim.step(wl.steps)
+    dphi = (sim.phi() - ref.phi()).abs().max().item()
+    say(f"  {precision}: max|dphi|={dphi:.2e}")
+    assert dphi <= tol_phi
 
 
 @pytest.mark.parametrize("streaming", STREAMING)

@@ -1,5 +1,7 @@
 """Pins of the oracle's lattices and MRT matrices (closed forms, identities)."""
+import dataclasses
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -136,3 +138,80 @@ def test_hydro_second_moment_relaxes_at_omega():
         om = 1.0 / tau
         want = Pi + om[None, None] * (Pieq - Pi)
         assert torch.abs(Pis - want).max() < 1e-15
+
+
+def _bulk_case(seed, s_bulk, N_shape=(3, 4, 2)):
+    rng = np.random.default_rng(seed)
+    grid = P.Grid(*N_shape, (True, True, True))
+    N = grid.N
+    prm = P.OracleParams(0.7, 0.55, 0.05, 4.0, 3e-4, 1.0, 0.3, (0, 0, 0), s_high=1.1,
+                         s_bulk=s_bulk)
+    phi = torch.tensor(rng.uniform(0.1, 0.9, N))
+    u = torch.tensor(rng.uniform(-0.01, 0.01, (3, N)))
+    h = P.equilibrium(L.D3Q15, phi, u, True)
+    g = P.equilibrium(L.D3Q27, torch.zeros(N), u, False) + \
+        1e-4 * torch.tensor(rng.standard_normal((27, N)))
+    return grid, prm, h, g
+
+
+def test_hydro_bulk_rate_relaxes_the_trace_of_the_stress():
+    """With a separate bulk rate s_b (MRT), the traceless part of Pi = sum c c g
+    relaxes at omega and its trace at s_b; mass and the forced first moment
+    are as without it; no moment of degree >= 3 changes."""
+    for sb in (1.0, 1.7):
+        grid, prm, h, g = _bulk_case(5, sb)
+        _, gs, aux = P.collide(grid, prm, h, g)
+        prm0 = dataclasses.replace(prm, s_bulk=0.0)
+        _, gs0, aux0 = P.collide(grid, prm0, h, g)
+        c = L.D3Q27.c
+        eye = torch.eye(3, dtype=torch.float64)[:, :, None]
+        Pi = torch.einsum("ia,ib,in->abn", c, c, g)
+        Pis = torch.einsum("ia,ib,in->abn", c, c, gs)
+        ueq = aux["u"]
+        X = aux["pstar"][None, None] * CS2 * eye + torch.einsum("an,bn->abn", ueq, ueq) - Pi
+        tr = (X[0, 0] + X[1, 1] + X[2, 2])[None, None] / 3.0 * eye
+        om = 1.0 / (prm.tau_L + aux["phi"] * (prm.tau_H - prm.tau_L))
+        want = Pi + om[None, None] * (X - tr) + sb * tr
+        assert torch.abs(Pis - want).max() < 1e-15
+        assert torch.abs(gs.sum(0) - g.sum(0)).max() < 1e-15
+        js = c.t() @ gs
+        assert torch.abs(js - (c.t() @ g + aux["F"] / aux["rho"][None])).max() < 1e-15
+        # moments of degree >= 3 of the two results agree (rows of the
+        # weighted-orthogonal moment matrix)
+        hi = L.D3Q27.degree >= 3
+        diff = L.D3Q27.M[hi] @ (gs - gs0)
+        assert torch.abs(diff).max() < 1e-15
+        assert torch.abs(L.D3Q27.M[hi] @ gs0).max() > 1e-6   # the check has content
+
+
+def test_viscous_force_reads_the_bulk_strain_with_its_own_rate():
+    """F_mu recovers (grad u + grad u^T) from Pi_neq mode by mode: a bulk
+    (trace) non-equilibrium is read with the bulk rate, so its force scales by
+    s_b / omega against s_b = 0; a traceless (shear) non-equilibrium gives the
+    same force whatever s_b is."""
+    grid = P.Grid(6, 5, 4, (True, True, True))
+    N = grid.N
+    x = torch.tensor(np.tile(np.arange(6), 20), dtype=torch.float64)
+    phi = 0.5 + 0.3 * torch.sin(2 * math.pi * x / 6)           # interface-like gradient
+    u = torch.zeros(3, N, dtype=torch.float64)
+    h = P.equilibrium(L.D3Q15, phi, u, True)
+    g0 = P.equilibrium(L.D3Q27, torch.zeros(N), u, False)
+    c, w = L.D3Q27.c, L.D3Q27.w
+    bulk = (w * ((c * c).sum(1) - 1.0))[:, None] * torch.ones(1, N, dtype=torch.float64)
+    shear = (w * c[:, 0] * c[:, 1])[:, None] * torch.ones(1, N, dtype=torch.float64)
+    sb = 1.3
+    base = P.OracleParams(0.7, 0.55, 0.05, 4.0, 0.0, 1.0, 0.3, (0, 0, 0))
+
+    def force(pert, s_bulk):
+        prm = dataclasses.replace(base, s_bulk=s_bulk)
+        return P.collide(grid, prm, h, g0 + 1e-3 * pert)[2]
+
+    ref = P.collide(grid, base, h, g0)[2]["F"]
+    a0, ab = force(bulk, 0.0), force(bulk, sb)
+    tau = base.tau_L + a0["phi"] * (base.tau_H - base.tau_L)
+    fmu0 = a0["F"] - ref
+    assert torch.abs(fmu0).max() > 1e-6
+    assert torch.abs((ab["F"] - ref) - (sb * tau)[None] * fmu0).max() < 1e-15
+    s0, ss = force(shear, 0.0), force(shear, sb)
+    assert torch.abs(s0["F"] - ref).max() > 1e-6
+    assert torch.abs(ss["F"] - s0["F"]).max() == 0.0

@@ -77,6 +77,7 @@ class Params:
     s_high: float = 1.0
     fp16_scale_log2: tuple = (12.0, 12.0)
     normal_eps: float = 1e-4
+    s_bulk: float = 0.0        # MRT rate of g's bulk mode; 0 = the second-order rate
 
     def copy(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
