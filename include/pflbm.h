@@ -109,8 +109,7 @@ typedef struct {
                              second-order moments, polynomial |c|^2 - 1): 0 = the
                              second-order rate omega(phi) (default), else in (0, 2).
                              The viscous force F_mu then recovers the trace part of
-                             the strain rate with this rate.  Ignored by BGK; the
-                             adjoint entry points accept only 0                   */
+                             the strain rate with this rate.  Ignored by BGK      */
 } pflbm_params;
 
 /* Bytes of device workspace for a context with this description (256-aligned
@@ -246,8 +245,7 @@ pflbm_status pflbm_adjoint_inject_phi(pflbm_ctx* ctx, const double* d_dl_dphi);
 /* One reverse step: lambda^{n+1} -> lambda^n through the step n -> n+1,
  * using the primal state of level n (a buffer written by pflbm_save_state
  * when the step count was n, or by pflbm_step_states with its phi^n formed),
- * and adds this step's contributions to dL/dM and dL/dsigma.  Returns
- * PFLBM_ERR_UNSUPPORTED for an MRT context whose s_bulk is not 0. */
+ * and adds this step's contributions to dL/dM and dL/dsigma. */
 pflbm_status pflbm_adjoint_step(pflbm_ctx* ctx, const void* d_state_n, int64_t n);
 
 /* Reverse of pflbm_init_equilibrium for phi0: d_dphi0 [N] (FP64) receives

@@ -67,8 +67,9 @@ __device__ __forceinline__ R second_moment_t(Dir d, const Sym<R>& L) {
 // Vector-Jacobian product of one cell's collision (S1-S15).  lh, lg: in =
 // adjoints of the post-collision populations, out = adjoints of the
 // pre-collision ones (the cell-local part).  Outputs the adjoints of the
-// stencil inputs (grad phi, lap phi) and of omega_phi and sigma.
-template <typename R, bool MRT>
+// stencil inputs (grad phi, lap phi) and of omega_phi and sigma.  BULK: the
+// bulk mode of g relaxes at P.s_bulk (MRT only).
+template <typename R, bool MRT, bool BULK>
 __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R Gx, R Gy, R Gz,
                                          R lap, const Phys<R>& P, const AdjConst<R>& K,
                                          R (&lh)[Q_H], R (&lg)[Q_G], R& lGx, R& lGy, R& lGz,
@@ -76,7 +77,8 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   // ---------------- forward recomputation ----------------
   const R phi = sum_h(h);
   const R rho = P.rho_L + phi * P.drho;
-  const R om = R(1) / (P.tau_L + phi * P.dtau);
+  const R tau = P.tau_L + phi * P.dtau;
+  const R om = R(1) / tau;
   const R theta = P.theta_k * phi * (R(1) - phi);
   const R rn = R(1) / sqrt(Gx * Gx + Gy * Gy + Gz * Gz + P.eps2);
   const R nx = Gx * rn, ny = Gy * rn, nz = Gz * rn;
@@ -97,9 +99,20 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   const Sym<R> Nq{Pi.xx - p3 - u1x * u1x, Pi.yy - p3 - u1y * u1y, Pi.zz - p3 - u1z * u1z,
                   Pi.xy - u1x * u1y, Pi.xz - u1x * u1z, Pi.yz - u1y * u1z};
   const R fm = -(R(1) - R(0.5) * om) * P.drho;
-  const R NGx = Nq.xx * Gx + Nq.xy * Gy + Nq.xz * Gz;
-  const R NGy = Nq.xy * Gx + Nq.yy * Gy + Nq.yz * Gz;
-  const R NGz = Nq.xz * Gx + Nq.yz * Gy + Nq.zz * Gz;
+  R NGx, NGy, NGz;
+  R kb = R(0), trN = R(0), tb = R(0);
+  if constexpr (BULK) {   // the trace of N enters F_mu scaled by s_bulk tau
+    kb = P.s_bulk * tau - R(1);
+    trN = Nq.xx + Nq.yy + Nq.zz;
+    tb = kb * trN * third;
+    NGx = (Nq.xx + tb) * Gx + Nq.xy * Gy + Nq.xz * Gz;
+    NGy = Nq.xy * Gx + (Nq.yy + tb) * Gy + Nq.yz * Gz;
+    NGz = Nq.xz * Gx + Nq.yz * Gy + (Nq.zz + tb) * Gz;
+  } else {
+    NGx = Nq.xx * Gx + Nq.xy * Gy + Nq.xz * Gz;
+    NGy = Nq.xy * Gx + Nq.yy * Gy + Nq.yz * Gz;
+    NGz = Nq.xz * Gx + Nq.yz * Gy + Nq.zz * Gz;
+  }
   const R Fx = F0x + fm * NGx, Fy = F0y + fm * NGy, Fz = F0z + fm * NGz;
   const R ux = jx + Fx * i2, uy = jy + Fy * i2, uz = jz + Fz * i2;
   const R uu = ux * ux + uy * uy + uz * uz;
@@ -205,10 +218,12 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   R l_base = R(0), l_fk = R(0), lFx = R(0), lFy = R(0), lFz = R(0), lom = R(0);
   R la1x = R(0), la1y = R(0), la1z = R(0);
   Sym<R> lA2{R(0), R(0), R(0), R(0), R(0), R(0)};
+  R Lb = R(0);   // sum_i lambda_i w_i (|c_i|^2 - 1): adjoint of the bulk-mode term
   {  // rest population
     const R w = R(wg(0));
     const R lam = lg[0];
     l_base += s * lam * w;
+    if constexpr (BULK) Lb -= lam * w;
     if (MRT) {
       hermite2_grad(cg(0), R(4.5) * dlo * lam * w, lA2);
       lom += lam * w * R(4.5) * hermite2(cg(0), A2);
@@ -224,6 +239,7 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
     const R sp = la + lb, sm = la - lb;
     const R cu = dot(d, ux, uy, uz);
     l_base += s * w * sp;
+    if constexpr (BULK) Lb += R(d.x * d.x + d.y * d.y + d.z * d.z - 1) * w * sp;
     const R lcu = s * w * (R(3) * sm + R(9) * cu * sp);
     if (d.x) lux += d.x > 0 ? lcu : -lcu;
     if (d.y) luy += d.y > 0 ? lcu : -lcu;
@@ -246,6 +262,14 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
       const R E = base + R(4.5) * cu * cu, O = R(3) * cu;
       lom += la * (w * (E + O) - g[k]) + lb * (w * (E - O) - g[k + 1]);
     }
+  }
+  if constexpr (MRT && BULK) {
+    // g*_i += 4.5 w_i (|c_i|^2 - 1) db, db = (s_bulk - omega) tr(A2) / 3
+    const R trA2 = A2.xx + A2.yy + A2.zz;
+    const R l_db = R(4.5) * Lb;
+    lom -= l_db * trA2 * third;
+    const R ltr = l_db * (P.s_bulk - om) * third;
+    lA2.xx += ltr; lA2.yy += ltr; lA2.zz += ltr;
   }
   lom += l_fk * (-R(1.5) / rho);
   R l_rho = -l_fk * fk / rho;
@@ -275,12 +299,22 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   // F = F0 + fm N G
   R lF0x = lFx, lF0y = lFy, lF0z = lFz;
   const R l_fm = lFx * NGx + lFy * NGy + lFz * NGz;
-  const Sym<R> lN{fm * lFx * Gx, fm * lFy * Gy, fm * lFz * Gz, fm * (lFx * Gy + lFy * Gx),
-                  fm * (lFx * Gz + lFz * Gx), fm * (lFy * Gz + lFz * Gy)};
+  Sym<R> lN{fm * lFx * Gx, fm * lFy * Gy, fm * lFz * Gz, fm * (lFx * Gy + lFy * Gx),
+            fm * (lFx * Gz + lFz * Gx), fm * (lFy * Gz + lFz * Gy)};
   lGx = fm * (Nq.xx * lFx + Nq.xy * lFy + Nq.xz * lFz);
   lGy = fm * (Nq.xy * lFx + Nq.yy * lFy + Nq.yz * lFz);
   lGz = fm * (Nq.xz * lFx + Nq.yz * lFy + Nq.zz * lFz);
   lom += R(0.5) * P.drho * l_fm;
+  R l_tau = R(0);
+  if constexpr (BULK) {   // tb = (s_bulk tau - 1) tr(N) / 3
+    lGx += fm * tb * lFx;
+    lGy += fm * tb * lFy;
+    lGz += fm * tb * lFz;
+    const R l_tb = fm * (lFx * Gx + lFy * Gy + lFz * Gz);
+    const R ltrN = l_tb * kb * third;
+    lN.xx += ltrN; lN.yy += ltrN; lN.zz += ltrN;
+    l_tau = l_tb * trN * third * P.s_bulk;
+  }
   // N = Pi - p/3 I - u1 u1^T
   lPi.xx += lN.xx; lPi.yy += lN.yy; lPi.zz += lN.zz;
   lPi.xy += lN.xy; lPi.xz += lN.xz; lPi.yz += lN.yz;
@@ -313,7 +347,7 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   lGz += rn * lnz - rn3 * Gln * Gz;
   // theta, omega, rho of phi
   l_phi += l_theta * P.theta_k * (R(1) - R(2) * phi);
-  l_phi += -lom * om * om * P.dtau;
+  l_phi += (l_tau - lom * om * om) * P.dtau;
   l_phi += l_rho * P.drho;
   l_omphi = lomp;
 
@@ -370,7 +404,7 @@ struct AdjArgs {
 template <typename S>
 struct AdjWaves { static constexpr int value = sizeof(S) == 8 ? 1 : PFLBM_ADJ_WAVES; };
 
-template <typename S, bool MRT, int RULE, bool MASK>
+template <typename S, bool MRT, int RULE, bool MASK, bool BULK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjWaves<S>::value)))
 void k_adj_cell(AdjArgs<S> a) {
   using St = Store<S>;
@@ -423,7 +457,7 @@ void k_adj_cell(AdjArgs<S> a) {
       lg[i] = *reinterpret_cast<const R*>(pair_base(a.lg_in, G.N, i) + off);
     }
     R lGx, lGy, lGz, lL, lomp, lsig;
-    cell_vjp<R, MRT>(h, g, Gx, Gy, Gz, lap, a.P, a.K, lh, lg, lGx, lGy, lGz, lL, lomp, lsig);
+    cell_vjp<R, MRT, BULK>(h, g, Gx, Gy, Gz, lap, a.P, a.K, lh, lg, lGx, lGy, lGz, lL, lomp, lsig);
 #pragma unroll
     for (int i = 0; i < Q_H; ++i) *slot(a.lh_out, G.N, i, idx) = lh[i];
 #pragma unroll

@@ -55,10 +55,23 @@ def _rel(a, b):
 @pytest.mark.parametrize("solids,nsteps,ckpt", [(False, 24, 5), (True, 23, 4), (False, 9, None)])
 def test_fp64_adjoint_matches_oracle_autograd(collision, solids, nsteps, ckpt):
     wl = _small(collision, solids)
+    say(f"case: adjoint fp64 {collision} solids={solids} N={nsteps} ckpt={ckpt}")
+    _adjoint_vs_oracle(wl, collision, nsteps, ckpt)
+
+
+@pytest.mark.parametrize("s_bulk,solids,nsteps,ckpt", [(1.3, True, 23, 4), (1.0, False, 24, 5)])
+def test_fp64_adjoint_with_a_bulk_rate_matches_oracle_autograd(s_bulk, solids, nsteps, ckpt):
+    """The reverse step with the bulk mode of g at its own rate (MRT)."""
+    wl = _small("mrt", solids)
+    wl = dataclasses.replace(wl, params=wl.params.copy(s_bulk=s_bulk))
+    say(f"case: adjoint fp64 mrt s_bulk={s_bulk} solids={solids} N={nsteps} ckpt={ckpt}")
+    _adjoint_vs_oracle(wl, "mrt", nsteps, ckpt)
+
+
+def _adjoint_vs_oracle(wl, collision, nsteps, ckpt):
     K = 3 if nsteps % 3 == 0 else 1
     rng = np.random.default_rng(5)
     target = rng.normal(0, 0.05, nsteps // K)
-    say(f"case: adjoint fp64 {collision} solids={solids} N={nsteps} ckpt={ckpt}")
     grid = OP.Grid(wl.nx, wl.ny, wl.nz, wl.periodic, wl.solid)
     prm = OP.OracleParams.from_workload(wl.params, collision)
     Lo, dphio, dMo, dso, tro = AD.loss_and_gradients(grid, prm, wl.phi0, wl.u0, wl.pstar0, nsteps,
@@ -195,23 +208,3 @@ def test_in_place_scheme_gives_the_same_gradients(precision, tol):
     say(f"  L {_rel(Lb, La):.1e} dM {_rel(Mb, Ma):.1e} dsigma {_rel(sb, sa):.1e} dphi0 {e_phi:.1e}")
     assert _rel(Lb, La) <= tol and _rel(Mb, Ma) <= tol and _rel(sb, sa) <= tol and e_phi <= tol
 
-
-def test_reverse_mode_refuses_a_bulk_rate():
-    """The hand-written reverse step is derived with the bulk mode relaxed at
-    omega(phi): an MRT context with s_bulk set is refused, not differentiated
-    wrongly; BGK (which ignores s_bulk) is accepted."""
-    from paper_2206_11637_amd._lib import PFLBMError
-    from paper_2206_11637_amd.sim import from_workload
-    wl = _small("mrt", False)
-    wl = dataclasses.replace(wl, params=wl.params.copy(s_bulk=1.0))
-    say("case: adjoint with s_bulk = 1 (mrt refused, bgk accepted)")
-    for collision in ("mrt", "bgk"):
-        sim = from_workload(wl, precision="fp64", collision=collision)
-        state = sim.save_state()
-        sim.adjoint_attach()
-        if collision == "mrt":
-            with pytest.raises(PFLBMError, match="s_bulk"):
-                sim.adjoint_step(state, 0)
-        else:
-            sim.adjoint_step(state, 0)
-            sim.sync()
