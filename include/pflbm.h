@@ -81,6 +81,15 @@ typedef enum { PFLBM_BGK = 0, PFLBM_MRT = 1 } pflbm_collision;
  *     step is a collide-and-stream kernel plus a light phi pass. */
 typedef enum { PFLBM_STREAM_AB = 0, PFLBM_STREAM_AA = 1 } pflbm_streaming;
 
+/* Source term of the hydrodynamic collision (the paper applies the forces
+ * with Guo's scheme in collision space, sec. "Lattice Boltzmann equations"):
+ *   PFLBM_FORCING_FIRST: 3 w_i c_i.F / rho, the first-order part (default);
+ *   PFLBM_FORCING_GUO:   Guo's full term w_i [3 (c_i - u) + 9 (c_i.u) c_i].F / rho,
+ *                        whose second moment (u F^T + F u^T)/rho removes the
+ *                        force's error term from the stress.
+ * Both are applied with the (I - S/2) factor of the collision's rates. */
+typedef enum { PFLBM_FORCING_FIRST = 0, PFLBM_FORCING_GUO = 1 } pflbm_forcing;
+
 typedef struct {
   int32_t nx, ny, nz;     /* cells per axis, each >= 1                            */
   uint32_t periodic;      /* bit0 x, bit1 y, bit2 z; clear bit = walls on that axis */
@@ -88,6 +97,7 @@ typedef struct {
   int32_t collision;      /* pflbm_collision                                      */
   int32_t has_mask;       /* 1: pflbm_set_mask must be called before init          */
   int32_t streaming;      /* pflbm_streaming                                      */
+  int32_t forcing;        /* pflbm_forcing (the reverse mode: FIRST only)          */
 } pflbm_desc;
 
 typedef struct {

@@ -38,7 +38,10 @@ One step n -> n+1 (paper sec. "Conservative Allen-Cahn model"):
       differences of u, as the paper remarks at the end of the LBE section)
   S11 F = F_s + F_b + F_p + F_mu ; u = j + F / (2 rho)
   S12 g^eq_i = w_i [p* + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u]  (eq. feq, rho_0 = 1)
-      F^g_i = 3 w_i c_i.F / rho
+      F^g_i = 3 w_i c_i.F / rho (first-order source, the default), or Guo's
+      full source w_i [3 (c_i - u) + 9 (c_i.u) c_i].F / rho (forcing="guo":
+      the paper names Guo's scheme; its second-order part adds
+      (u F^T + F u^T)/rho to the second moment of the source)
   S13 g*_i = g_i + [M^-1 S M (g^eq - g)]_i + [M^-1 (I - S/2) M F^g]_i
   S14 h^eq_i = phi w_i [1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u] ; F^h_i = w_i theta c_i.n
   S15 h*_i = h_i + [M^-1 S M (h^eq - h)]_i + [M^-1 (I - S/2) M F^h]_i
@@ -85,12 +88,13 @@ class OracleParams:
     collision: str = "mrt"  # "mrt" or "bgk"
     eps_normal: float = 1e-4
     s_bulk: float = 0.0     # 0: the bulk mode of g relaxes with omega(phi)
+    forcing: str = "first"  # "first" or "guo" (source of the g collision, S12)
 
     @classmethod
-    def from_workload(cls, p, collision="mrt") -> "OracleParams":
+    def from_workload(cls, p, collision="mrt", forcing="first") -> "OracleParams":
         return cls(p.tau_H, p.tau_L, p.mobility, p.xi, p.sigma, p.rho_H, p.rho_L,
                    tuple(p.g), p.s_high, collision, p.normal_eps,
-                   float(getattr(p, "s_bulk", 0.0)))
+                   float(getattr(p, "s_bulk", 0.0)), forcing)
 
 
 class Grid:
@@ -235,11 +239,20 @@ def collide(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
     u = j + F / (2.0 * rho[None, :])
     # S12, S13
     geq = equilibrium(LG, pstar, u, False)
-    Fg = 3.0 * LG.w[:, None] * (LG.c @ F) / rho[None, :]
+    cF = LG.c @ F                        # [q, N]
+    if prm.forcing == "guo":
+        cu = LG.c @ u
+        uF = (u * F).sum(0)
+        Fg = LG.w[:, None] * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF[None, :]) / rho[None, :]
+    elif prm.forcing == "first":
+        Fg = 3.0 * LG.w[:, None] * cF / rho[None, :]
+    else:
+        raise ValueError(prm.forcing)
     sg = _rates(LG, omega, prm.s_high, bgk, N)
     gstar = g + mrt_apply(LG, sg, geq - g) + mrt_apply(LG, 1.0 - 0.5 * sg, Fg)
-    if bulk:   # the source 3 w c.F / rho is odd in c: no bulk component
-        gstar = gstar + (prm.s_bulk - omega)[None, :] * bulk_part(LG, geq - g)
+    if bulk:   # the bulk mode at s_b: relaxation s_b, source factor 1 - s_b/2
+        sb = (prm.s_bulk - omega)[None, :]
+        gstar = gstar + sb * bulk_part(LG, geq - g) - 0.5 * sb * bulk_part(LG, Fg)
     # S14, S15
     heq = equilibrium(LH, phi, u, True)
     Fh = LH.w[:, None] * theta[None, :] * (LH.c @ normal)

@@ -11,13 +11,14 @@ PFLBM_OK, PFLBM_ERR_ARG, PFLBM_ERR_STATE, PFLBM_ERR_HIP, PFLBM_ERR_UNSTABLE, \
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16s": 2}
 COLLISIONS = {"bgk": 0, "mrt": 1}
 STREAMING = {"ab": 0, "aa": 1}
+FORCING = {"first": 0, "guo": 1}
 STATES_WRITE_SRC_PHI, STATES_SKIP_DST_PHI = 1, 2
 
 
 class Desc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("periodic", C.c_uint32), ("precision", C.c_int32), ("collision", C.c_int32),
-                ("has_mask", C.c_int32), ("streaming", C.c_int32)]
+                ("has_mask", C.c_int32), ("streaming", C.c_int32), ("forcing", C.c_int32)]
 
 
 class Params(C.Structure):

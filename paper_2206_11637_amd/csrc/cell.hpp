@@ -225,7 +225,10 @@ __device__ __forceinline__ void relax_pairs(R (&f)[Q], R shi, R e0, const Sym<R>
 // + 9/2 (c.u)^2 - 3/2 u.u]; moments of Delta = g^eq - g: a1 = u - j,
 // A2 = p/3 I + u u - Pi; Guo source 3 w c.F / rho applied with (1 - omega/2).
 // With s_bulk set, the trace part of the second-order relaxation uses it.
-template <typename R, bool MRT>
+// GUO: Guo's full source, whose second-order part 4.5 w (c c - I/3):S / rho,
+// S = u F^T + F u^T, is applied with (1 - omega/2) (its bulk part with
+// (1 - s_bulk/2) when that rate is set).
+template <typename R, bool MRT, bool GUO>
 __device__ __forceinline__ void collide_g(R (&g)[Q_G], const CellState<R>& c, const Phys<R>& P) {
   const R uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
   const R om = c.omega;
@@ -251,6 +254,18 @@ __device__ __forceinline__ void collide_g(R (&g)[Q_G], const CellState<R>& c, co
     Vx += d3 * (c.ux - c.jx);
     Vy += d3 * (c.uy - c.jy);
     Vz += d3 * (c.uz - c.jz);
+  }
+  if constexpr (GUO) {
+    const R kf = (R(1) - R(0.5) * om) / c.rho;
+    const R Sxx = R(2) * c.ux * c.Fx, Syy = R(2) * c.uy * c.Fy, Szz = R(2) * c.uz * c.Fz;
+    const R trS = Sxx + Syy + Szz;
+    const R kd = (MRT && P.s_bulk > R(0)) ? R(0.5) * (om - P.s_bulk) / c.rho * trS * (R(1) / R(3))
+                                          : R(0);
+    B.xx += kf * Sxx + kd; B.yy += kf * Syy + kd; B.zz += kf * Szz + kd;
+    B.xy += kf * (c.ux * c.Fy + c.uy * c.Fx);
+    B.xz += kf * (c.ux * c.Fz + c.uz * c.Fx);
+    B.yz += kf * (c.uy * c.Fz + c.uz * c.Fy);
+    e0 -= R(1.5) * kf * trS + R(4.5) * kd;
   }
   relax_pairs<R, true, Q_G>(g, shi, e0, B, Vx, Vy, Vz);
 }

@@ -528,7 +528,7 @@ struct StepArgs {
 // Fused step n -> n+1: pull, phi^n and its stencils, collide both lattices,
 // store.  One barrier per plane; the 4-plane ring lets plane z+1 be written
 // while plane z-1 is still being read.
-template <typename S, bool MRT, bool MASK>
+template <typename S, bool MRT, bool MASK, bool GUO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<S>::value)))
 void k_step(StepArgs<S> a) {
   using St = Store<S>;
@@ -638,7 +638,7 @@ void k_step(StepArgs<S> a) {
       const R phi = p0[opos];
       CellState<R> c;
       prologue(phi, sum_h(h), g, Gx, Gy, Gz, lap, a.P, c);
-      collide_g<R, MRT>(g, c, a.P);
+      collide_g<R, MRT, GUO>(g, c, a.P);
       collide_h<R, MRT>(h, c, a.P);
       if (St::kShift) a.phi_out[idx] = phi;
       if (a.phi_src_out) a.phi_src_out[idx] = phi;
@@ -678,7 +678,7 @@ template <bool ODD> struct AaPolicy {
 // In-place AA collide-and-stream of both lattices for one plane of one tile
 // (phi^n staged in LDS).  Also runs out of place (h_in != h) between saved
 // states.
-template <typename S, bool MRT, bool ODD, bool MASK>
+template <typename S, bool MRT, bool ODD, bool MASK, bool GUO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<S>::value)))
 void k_cell_aa(CellArgs<S> a) {
   using St = Store<S>;
@@ -710,7 +710,7 @@ void k_cell_aa(CellArgs<S> a) {
   stencil3(pm, p0, pp, TX, lx, ly, Gx, Gy, Gz, lap);
   CellState<R> c;
   prologue(phi, sum_h(h), g, Gx, Gy, Gz, lap, a.P, c);
-  collide_g<R, MRT>(g, c, a.P);
+  collide_g<R, MRT, GUO>(g, c, a.P);
   collide_h<R, MRT>(h, c, a.P);
   const Planes<R> pl{pm, p0, pp, TX, lx, ly};
   store_aa<S, ODD, AaPolicy<ODD>::nt_store>(a.h, a.g, G.N, idx, nb, walls, a.cd, ref, phi, pl, h, g);

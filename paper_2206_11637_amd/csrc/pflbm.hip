@@ -33,6 +33,7 @@ bool desc_ok(const pflbm_desc* d) {
   if (d->collision < 0 || d->collision > 1) return false;
   if (d->periodic > 7u) return false;
   if (d->streaming < 0 || d->streaming > 1) return false;
+  if (d->forcing < 0 || d->forcing > 1) return false;
   const long long N = (long long)d->nx * d->ny * d->nz;
   // population addressing uses 32-bit byte offsets within each opposite pair
   // of populations (and within the FP32/FP64 adjoint arrays of one population)
@@ -254,19 +255,25 @@ StepArgs<S> step_args(pflbm_ctx* c) {
   return a;
 }
 
+template <typename S, bool MRT, bool GUO>
+void launch_step_k(pflbm_ctx* c, const StepArgs<S>& a, dim3 grd, dim3 blk, size_t sm) {
+  if (c->d.has_mask) hipLaunchKernelGGL((k_step<S, MRT, true, GUO>), grd, blk, sm, c->stream, a);
+  else hipLaunchKernelGGL((k_step<S, MRT, false, GUO>), grd, blk, sm, c->stream, a);
+}
+
 template <typename S>
 void launch_step(pflbm_ctx* c, const StepArgs<S>& a) {
   using R = typename Store<S>::R;
   // 4-plane phi ring + two planes of the threads' own h
   const size_t sm = ((size_t)4 * (c->L.bx + 2) * (c->L.by + 2) + 2 * Q_H * 256) * sizeof(R);
   const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks_step);
-  const bool mrt = c->d.collision == PFLBM_MRT, m = c->d.has_mask;
+  const bool mrt = c->d.collision == PFLBM_MRT, guo = c->d.forcing == PFLBM_FORCING_GUO;
   if (mrt) {
-    if (m) hipLaunchKernelGGL((k_step<S, true, true>), grd, blk, sm, c->stream, a);
-    else hipLaunchKernelGGL((k_step<S, true, false>), grd, blk, sm, c->stream, a);
+    if (guo) launch_step_k<S, true, true>(c, a, grd, blk, sm);
+    else launch_step_k<S, true, false>(c, a, grd, blk, sm);
   } else {
-    if (m) hipLaunchKernelGGL((k_step<S, false, true>), grd, blk, sm, c->stream, a);
-    else hipLaunchKernelGGL((k_step<S, false, false>), grd, blk, sm, c->stream, a);
+    if (guo) launch_step_k<S, false, true>(c, a, grd, blk, sm);
+    else launch_step_k<S, false, false>(c, a, grd, blk, sm);
   }
 }
 
@@ -343,13 +350,19 @@ CellArgs<S> aa_args(pflbm_ctx* c) {
   return a;
 }
 
-template <typename S, bool MRT, bool ODD>
-void launch_aa_m(pflbm_ctx* c, const CellArgs<S>& a) {
+template <typename S, bool MRT, bool ODD, bool GUO>
+void launch_aa_g(pflbm_ctx* c, const CellArgs<S>& a) {
   using R = typename Store<S>::R;
   const size_t sm = (size_t)(c->L.bx + 2) * (c->L.by + 2) * 3 * sizeof(R);
   const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks);
-  if (c->d.has_mask) hipLaunchKernelGGL((k_cell_aa<S, MRT, ODD, true>), grd, blk, sm, c->stream, a);
-  else hipLaunchKernelGGL((k_cell_aa<S, MRT, ODD, false>), grd, blk, sm, c->stream, a);
+  if (c->d.has_mask) hipLaunchKernelGGL((k_cell_aa<S, MRT, ODD, true, GUO>), grd, blk, sm, c->stream, a);
+  else hipLaunchKernelGGL((k_cell_aa<S, MRT, ODD, false, GUO>), grd, blk, sm, c->stream, a);
+}
+
+template <typename S, bool MRT, bool ODD>
+void launch_aa_m(pflbm_ctx* c, const CellArgs<S>& a) {
+  if (c->d.forcing == PFLBM_FORCING_GUO) launch_aa_g<S, MRT, ODD, true>(c, a);
+  else launch_aa_g<S, MRT, ODD, false>(c, a);
 }
 
 template <typename S>

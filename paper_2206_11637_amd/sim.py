@@ -50,8 +50,9 @@ class Simulation:
 
     def __init__(self, nx: int, ny: int, nz: int, periodic=(True, False, True),
                  precision: str = "fp32", collision: str = "mrt", solid=None, params=None,
-                 device: str = "cuda:0", streaming: str = "ab"):
+                 device: str = "cuda:0", streaming: str = "ab", forcing: str = "first"):
         self.streaming = streaming
+        self.forcing = forcing
         self.lib = load()
         self.device = torch.device(device)
         self.shape = (nz, ny, nx)
@@ -60,7 +61,7 @@ class Simulation:
         pbits = int(bool(periodic[0])) | (int(bool(periodic[1])) << 1) | (int(bool(periodic[2])) << 2)
         self.desc = Desc(nx, ny, nz, pbits, _lib.PRECISIONS[precision],
                          _lib.COLLISIONS[collision], int(solid is not None),
-                         _lib.STREAMING[streaming])
+                         _lib.STREAMING[streaming], _lib.FORCING[forcing])
         nbytes = self.lib.pflbm_workspace_bytes(C.byref(self.desc))
         if nbytes == 0:
             raise ValueError(f"invalid lattice description {nx}x{ny}x{nz}")
@@ -208,10 +209,11 @@ class Simulation:
 
 
 def from_workload(wl, precision="fp32", collision="mrt", device="cuda:0", params=None,
-                  streaming="ab") -> Simulation:
+                  streaming="ab", forcing="first") -> Simulation:
     """Simulation for a workloads.Workload, initialised at equilibrium.
-    streaming: "ab" (two buffers, fused step) or "aa" (in place)."""
+    streaming: "ab" (two buffers, fused step) or "aa" (in place);
+    forcing: "first" (first-order source) or "guo" (Guo's full source)."""
     sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, precision, collision, wl.solid,
-                     params if params is not None else wl.params, device, streaming)
+                     params if params is not None else wl.params, device, streaming, forcing)
     sim.init_equilibrium(wl.phi0, wl.u0, wl.pstar0)
     return sim

@@ -50,8 +50,12 @@ def test_workspace_sizes_and_invalid_descriptions():
     assert (42 * 4 + 8) * N <= lib.pflbm_workspace_bytes(C.byref(a32)) < (2 * 42 * 4) * N
     for bad in (L.Desc(0, 4, 4, 0, 0, 0, 0), L.Desc(4, 4, 4, 9, 0, 0, 0),
                 L.Desc(4, 4, 4, 0, 3, 0, 0), L.Desc(4, 4, 4, 0, 0, 2, 0),
-                L.Desc(4, 4, 4, 0, 0, 0, 0, 2)):
+                L.Desc(4, 4, 4, 0, 0, 0, 0, 2), L.Desc(4, 4, 4, 0, 0, 0, 0, 0, 2),
+                L.Desc(4, 4, 4, 0, 0, 0, 0, 0, -1)):
         assert lib.pflbm_workspace_bytes(C.byref(bad)) == 0
+    # Guo's full source is a kernel variant: the same workspace
+    assert lib.pflbm_workspace_bytes(C.byref(L.Desc(8, 8, 8, 7, 1, 1, 0, 0, 1))) == \
+        lib.pflbm_workspace_bytes(C.byref(L.Desc(8, 8, 8, 7, 1, 1, 0, 0, 0)))
     ctx = C.c_void_p()
     assert lib.pflbm_create(C.byref(L.Desc(0, 4, 4, 0, 0, 0, 0)), C.c_void_p(256), 1 << 20,
                             None, C.byref(ctx)) == L.PFLBM_ERR_ARG

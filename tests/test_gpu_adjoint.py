@@ -208,3 +208,16 @@ def test_in_place_scheme_gives_the_same_gradients(precision, tol):
     say(f"  L {_rel(Lb, La):.1e} dM {_rel(Mb, Ma):.1e} dsigma {_rel(sb, sa):.1e} dphi0 {e_phi:.1e}")
     assert _rel(Lb, La) <= tol and _rel(Mb, Ma) <= tol and _rel(sb, sa) <= tol and e_phi <= tol
 
+
+def test_reverse_mode_refuses_guos_full_source():
+    """The reverse step is derived for the first-order source: a context with
+    Guo's full source is refused rather than differentiated wrongly."""
+    from paper_2206_11637_amd._lib import PFLBMError
+    from paper_2206_11637_amd.sim import from_workload
+    wl = _small("mrt", False)
+    say("case: adjoint with forcing=guo (refused)")
+    sim = from_workload(wl, precision="fp64", forcing="guo")
+    state = sim.save_state()
+    sim.adjoint_attach()
+    with pytest.raises(PFLBMError, match="first-order source"):
+        sim.adjoint_step(state, 0)

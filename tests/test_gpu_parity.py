@@ -133,6 +133,49 @@ def test_bulk_mode_rate_in_reduced_precision(precision, tol_phi):
 
 
 @pytest.mark.parametrize("streaming", STREAMING)
+@pytest.mark.parametrize("collision,s_bulk", [("mrt", 0.0), ("bgk", 0.0), ("mrt", 1.2)])
+def test_full_guo_source_matches_oracle(collision, s_bulk, streaming):
+    """Guo's full source for g (forcing="guo"): FP64 parity on a walled ragged
+    grid with solids and gravity, with and without a bulk rate."""
+    p = W.Params(tau_H=0.6, tau_L=0.7, mobility=0.05, xi=4.0, sigma=5e-4, rho_L=0.05,
+                 g=(1e-5, -2e-5, 0.0), s_bulk=s_bulk)
+    wl = W.random_state(37, 19, 6, periodic=(False, False, True), params=p,
+                        solid_fraction=0.1, seed=43, steps=8, u_amp=0.02)
+    say(f"case: guo forcing {collision} s_bulk={s_bulk} {streaming}")
+    grid = OP.Grid(wl.nx, wl.ny, wl.nz, wl.periodic, wl.solid)
+    prm = OP.OracleParams.from_workload(wl.params, collision, "guo")
+    h, g = OP.init_equilibrium(grid, wl.phi0, wl.u0, wl.pstar0)
+    from paper_2206_11637_amd.sim import from_workload
+    sim = from_workload(wl, precision="fp64", collision=collision, streaming=streaming,
+                        forcing="guo")
+    h, g = OP.run(grid, prm, h, g, wl.steps)
+    sim.step(wl.steps)
+    _compare_fields(sim, grid, prm, h, g, TOL64, f"guo {collision} after {wl.steps}")
+    # and the source makes a difference against the first-order one
+    first = from_workload(wl, precision="fp64", collision=collision, streaming=streaming)
+    first.step(wl.steps)
+    fl = torch.as_tensor(~wl.solid.reshape(-1), device=sim.device)
+    d = (first.populations()[1][:, fl] - sim.populations()[1][:, fl]).abs().max().item()
+    assert d > 1e-9, d
+
+
+@pytest.mark.parametrize("precision,tol_phi", [("fp32", 1e-6), ("fp16s", 2e-4)])
+def test_full_guo_source_in_reduced_precision(precision, tol_phi):
+    """Guo's full source in the FP32 forms against the FP64 path (capillary
+    wave, 200 steps)."""
+    from paper_2206_11637_amd.sim import from_workload
+    wl = W.config0()
+    say(f"case: config0 guo {precision} vs fp64")
+    ref = from_workload(wl, precision="fp64", forcing="guo")
+    ref.step(wl.steps)
+    sim = from_workload(wl, precision=precision, forcing="guo")
+    sim.step(wl.steps)
+    dphi = (sim.phi() - ref.phi()).abs().max().item()
+    say(f"  {precision}: max|dphi|={dphi:.2e}")
+    assert dphi <= tol_phi
+
+
+@pytest.mark.parametrize("streaming", STREAMING)
 def test_zero_steps_and_resume_are_bitwise(streaming):
     wl = W.random_state(70, 21, 13, periodic=(True, False, True), solid_fraction=0.05, seed=4)
     say(f"case: resume 70x21x13 {streaming}")

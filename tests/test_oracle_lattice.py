@@ -215,3 +215,35 @@ def test_viscous_force_reads_the_bulk_strain_with_its_own_rate():
     s0, ss = force(shear, 0.0), force(shear, sb)
     assert torch.abs(s0["F"] - ref).max() > 1e-6
     assert torch.abs(ss["F"] - s0["F"]).max() == 0.0
+
+
+@pytest.mark.parametrize("coll,sb", [("mrt", 0.0), ("bgk", 0.0), ("mrt", 1.3)])
+def test_full_guo_source_adds_its_second_moment_to_the_stress(coll, sb):
+    """Guo's full source w_i [3 (c - u) + 9 (c.u) c].F / rho has zeroth moment
+    0, first F/rho and second (u F^T + F u^T)/rho.  Against the first-order
+    source, the collision then changes nothing but the stress, by
+    (1 - omega/2)(u F^T + F u^T)/rho in its traceless part and (1 - s_b/2)
+    in its trace (s_b = omega without a bulk rate); no moment of degree >= 3
+    moves."""
+    grid, prm, h, g = _bulk_case(9, sb)
+    prm = dataclasses.replace(prm, collision=coll)
+    _, g1, a1 = P.collide(grid, dataclasses.replace(prm, forcing="first"), h, g)
+    _, g2, a2 = P.collide(grid, dataclasses.replace(prm, forcing="guo"), h, g)
+    for k in ("F", "u", "rho"):
+        assert torch.equal(a1[k], a2[k])
+    c = L.D3Q27.c
+    u, F, rho = a1["u"], a1["F"], a1["rho"]
+    assert torch.abs(g2.sum(0) - g1.sum(0)).max() < 1e-16
+    assert torch.abs(c.t() @ (g2 - g1)).max() < 1e-16
+    S = (torch.einsum("an,bn->abn", u, F) + torch.einsum("an,bn->abn", F, u)) / rho[None, None]
+    eye = torch.eye(3, dtype=torch.float64)[:, :, None]
+    trS = (S[0, 0] + S[1, 1] + S[2, 2])[None, None] / 3.0 * eye
+    om = 1.0 / (prm.tau_L + a1["phi"] * (prm.tau_H - prm.tau_L))
+    s_tr = om if (sb == 0.0 or coll == "bgk") else torch.full_like(om, sb)
+    want = (1 - 0.5 * om)[None, None] * (S - trS) + (1 - 0.5 * s_tr)[None, None] * trS
+    dPi = torch.einsum("ia,ib,in->abn", c, c, g2 - g1)
+    assert torch.abs(S).max() > 1e-9
+    assert torch.abs(dPi - want).max() < 1e-17
+    if coll == "mrt":
+        hi = L.D3Q27.degree >= 3
+        assert torch.abs(L.D3Q27.M[hi] @ (g2 - g1)).max() < 1e-17
