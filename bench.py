@@ -32,23 +32,26 @@ CELL_KERNEL_BYTES = STEP_BYTES
 # the in-place AA scheme's collide-and-stream kernel alone: populations once
 # each way and phi read once (its separate phi pass writes phi)
 AA_CELL_KERNEL_BYTES = {"fp64": 680, "fp32": 340, "fp16s": 172}
+# the D3Q27-phase build: 27 + 27 populations
+STEP_BYTES_D3Q27 = {"fp64": 880, "fp32": 440, "fp16s": 224}
 # HBM bytes per launch of k_step on the rising-bubble lattice from rocprofv3
 # FETCH_SIZE / WRITE_SIZE, scaled by the factors a plain 2 GiB device copy
 # gives on the same box (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE); taken for
 # the current kernel (profiles/k_step_rising_bubble_128x512x128_hbm_traffic.txt)
 # and to be re-measured whenever it changes
-TRAFFIC = {"fp32": 3.405e9, "fp16s": 1.558e9, "fp64": 6.037e9}
+TRAFFIC = {"fp32": 3.404e9, "fp16s": 1.558e9, "fp64": 6.037e9}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_form(wl, precision, steps, warmup, collision="mrt", streaming="ab"):
+def time_form(wl, precision, steps, warmup, collision="mrt", streaming="ab", phase="d3q15"):
     import torch
 
     from paper_2206_11637_amd.sim import from_workload
-    sim = from_workload(wl, precision=precision, collision=collision, streaming=streaming)
+    sim = from_workload(wl, precision=precision, collision=collision, streaming=streaming,
+                        phase_lattice=phase)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -62,13 +65,17 @@ def time_form(wl, precision, steps, warmup, collision="mrt", streaming="ab"):
     cells = wl.cells
     mlups = cells * steps / (wall_ms * 1e-3) / 1e6
     cell_avg = cell_ms / steps
-    kb = (AA_CELL_KERNEL_BYTES if streaming == "aa" else CELL_KERNEL_BYTES)[precision]
+    if phase == "d3q27":
+        kb = sb = STEP_BYTES_D3Q27[precision]
+    else:
+        kb = (AA_CELL_KERNEL_BYTES if streaming == "aa" else CELL_KERNEL_BYTES)[precision]
+        sb = STEP_BYTES[precision]
     achieved = kb * cells / (cell_avg * 1e-3) / 1e9
     out = dict(mlups=mlups, ms_per_step=wall_ms / steps, cell_kernel_ms=cell_avg,
                phi_kernel_ms=phi_ms / steps, cell_kernel_GBps=achieved,
                cell_kernel_frac=achieved / HBM_PEAK_GBPS,
-               effective_GBps=mlups * STEP_BYTES[precision] / 1e3,
-               effective_frac=mlups * STEP_BYTES[precision] / 1e3 / HBM_PEAK_GBPS,
+               effective_GBps=mlups * sb / 1e3,
+               effective_frac=mlups * sb / 1e3 / HBM_PEAK_GBPS,
                mass=r[0])
     del sim
     torch.cuda.empty_cache()
@@ -285,6 +292,9 @@ def main():
         # the in-place AA scheme: half the population memory, a separate phi pass
         form("fp32_in_place_aa_rising_bubble_128x512x128", time_form, wl1, "fp32", half, args.warmup,
              "mrt", "aa")
+        # the D3Q27 phase lattice (the paper's 3D choice; a separate build)
+        form("fp32_d3q27_phase_rising_bubble_128x512x128", time_form, wl1, "fp32", half,
+             args.warmup, "mrt", "ab", "d3q27")
         del wl1
         wl2 = W.config2()
         form("fp32_drop_impact_384^3", time_form, wl2, "fp32", half, args.warmup)

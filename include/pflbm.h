@@ -226,9 +226,16 @@ pflbm_status pflbm_profile_step(pflbm_ctx* ctx, int64_t nsteps, double out_ms_ho
 /* Waits for all work on the context's stream. */
 pflbm_status pflbm_sync(pflbm_ctx* ctx);
 
-/* Host copy of the library's velocity set for q = 15 (D3Q15) or 27 (D3Q27):
- * c_out [q][3] integers, w_out [q] weights.  Either may be NULL. */
+/* Host copy of the library's velocity set for q = pflbm_phase_q() (the phase
+ * field's) or 27 (the hydrodynamics'): c_out [q][3] integers, w_out [q]
+ * weights.  Either may be NULL. */
 pflbm_status pflbm_lattice(int32_t q, int32_t* c_out, double* w_out);
+
+/* Velocity count of this build's phase lattice: 15 (D3Q15, libpflbm.so) or
+ * 27 (D3Q27, the velocity set the paper uses for both lattices in 3D:
+ * libpflbm_d3q27.so, the same interface built with PFLBM_PHASE_D3Q27).  Every
+ * "[15][N]" phase-field array of this interface has pflbm_phase_q() rows. */
+int32_t pflbm_phase_q(void);
 
 /* ---------------------------------------------------------------------------
  * Reverse mode (adjoint) of the step, for gradients of a loss of the phase

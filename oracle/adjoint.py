@@ -23,7 +23,7 @@ from . import pflbm as P
 def rollout_trace(grid: P.Grid, prm: P.OracleParams, phi0: torch.Tensor, u0, pstar0,
                   nsteps: int, sample_every: int, depth: float, x0: int = 0):
     """Amplitude samples a(sample_every), a(2 sample_every), ..., a(nsteps)."""
-    h, g = P.init_equilibrium(grid, phi0, u0, pstar0)
+    h, g = P.init_equilibrium(grid, phi0, u0, pstar0, prm.phase_lattice)
     out = []
     for n in range(1, nsteps + 1):
         h, g = P.step(grid, prm, h, g)

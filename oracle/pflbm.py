@@ -5,7 +5,8 @@ float64, vectorised over cells but otherwise taking the steps of the method
 in the order below, with two-buffer (A -> B) streaming and dense
 M^-1 S M collision matrices.  Nothing here is shared with the HIP library.
 
-State: h [15, N] (phase field, D3Q15) and g [27, N] (hydrodynamics, D3Q27),
+State: h [15, N] (phase field, D3Q15; [27, N] with the D3Q27 phase lattice the
+paper uses in 3D, phase_lattice="d3q27") and g [27, N] (hydrodynamics, D3Q27),
 post-streaming, with N = nx*ny*nz cells and cell index x + nx*(y + ny*z).
 Solid cells hold zeros and are never updated.
 
@@ -89,12 +90,23 @@ class OracleParams:
     eps_normal: float = 1e-4
     s_bulk: float = 0.0     # 0: the bulk mode of g relaxes with omega(phi)
     forcing: str = "first"  # "first" or "guo" (source of the g collision, S12)
+    phase_lattice: str = "d3q15"  # or "d3q27" (the paper's own 3D phase lattice)
 
     @classmethod
-    def from_workload(cls, p, collision="mrt", forcing="first") -> "OracleParams":
+    def from_workload(cls, p, collision="mrt", forcing="first",
+                      phase_lattice="d3q15") -> "OracleParams":
         return cls(p.tau_H, p.tau_L, p.mobility, p.xi, p.sigma, p.rho_H, p.rho_L,
                    tuple(p.g), p.s_high, collision, p.normal_eps,
-                   float(getattr(p, "s_bulk", 0.0)), forcing)
+                   float(getattr(p, "s_bulk", 0.0)), forcing, phase_lattice)
+
+
+def phase_lattice(name: str) -> Lattice:
+    """Velocity set of the phase field: D3Q15 (default) or D3Q27."""
+    if name == "d3q15":
+        return D3Q15
+    if name == "d3q27":
+        return D3Q27
+    raise ValueError(name)
 
 
 class Grid:
@@ -181,7 +193,7 @@ def _rates(lat: Lattice, low: torch.Tensor, s_high, bgk: bool, n: int) -> torch.
 
 def collide(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
     """S1-S15.  Returns (h*, g*, aux) where aux holds the cell moments and forces."""
-    LH, LG = D3Q15, D3Q27
+    LH, LG = phase_lattice(prm.phase_lattice), D3Q27
     N = grid.N
     bgk = prm.collision == "bgk"
     drho = prm.rho_H - prm.rho_L
@@ -278,7 +290,7 @@ def stream(grid: Grid, lat: Lattice, fstar: torch.Tensor) -> torch.Tensor:
 
 def step(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
     hs, gs, _ = collide(grid, prm, h, g)
-    return stream(grid, D3Q15, hs), stream(grid, D3Q27, gs)
+    return stream(grid, phase_lattice(prm.phase_lattice), hs), stream(grid, D3Q27, gs)
 
 
 def run(grid: Grid, prm: OracleParams, h, g, nsteps: int):
@@ -287,15 +299,16 @@ def run(grid: Grid, prm: OracleParams, h, g, nsteps: int):
     return h, g
 
 
-def init_equilibrium(grid: Grid, phi0, u0, pstar0):
+def init_equilibrium(grid: Grid, phi0, u0, pstar0, phase: str = "d3q15"):
     """h = phi0 w_i [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u], g = g^eq(p*0, u0); zero in solids.
 
-    phi0 [N] or [nz,ny,nx]; u0 [3, ...]; pstar0 like phi0 (numpy or torch).
+    phi0 [N] or [nz,ny,nx]; u0 [3, ...]; pstar0 like phi0 (numpy or torch);
+    phase: the phase field's velocity set ("d3q15" or "d3q27").
     """
     phi0 = torch.as_tensor(phi0, dtype=F64).reshape(-1)
     u0 = torch.as_tensor(u0, dtype=F64).reshape(3, -1)
     pstar0 = torch.as_tensor(pstar0, dtype=F64).reshape(-1)
-    h = equilibrium(D3Q15, phi0, u0, True)
+    h = equilibrium(phase_lattice(phase), phi0, u0, True)
     g = equilibrium(D3Q27, pstar0, u0, False)
     fl = grid.fluid[None, :]
     return torch.where(fl, h, torch.zeros_like(h)), torch.where(fl, g, torch.zeros_like(g))

@@ -5,6 +5,8 @@ import ctypes as C
 import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpflbm.so")
+LIB_PATHS = {"d3q15": LIB_PATH,
+             "d3q27": os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpflbm_d3q27.so")}
 
 PFLBM_OK, PFLBM_ERR_ARG, PFLBM_ERR_STATE, PFLBM_ERR_HIP, PFLBM_ERR_UNSTABLE, \
     PFLBM_ERR_UNSUPPORTED = range(6)
@@ -52,6 +54,7 @@ SIGNATURES = {
     "pflbm_profile_step": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double)]),
     "pflbm_sync": (C.c_int, [C.c_void_p]),
     "pflbm_lattice": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "pflbm_phase_q": (C.c_int32, []),
     "pflbm_adjoint_workspace_bytes": (C.c_size_t, [C.POINTER(Desc)]),
     "pflbm_adjoint_attach": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "pflbm_adjoint_reset": (C.c_int, [C.c_void_p]),
@@ -63,16 +66,19 @@ SIGNATURES = {
     "pflbm_last_error": (C.c_char_p, [C.c_void_p]),
 }
 
-_lib = None
+_libs = {}
+_ctx_lib = {}
 
 
-def load(path: str = None):
-    """Load libpflbm.so (or the build named by $PFLBM_LIBRARY); raises if it is
-    missing (there is no fallback path)."""
-    global _lib
-    if _lib is not None:
-        return _lib
-    path = path or os.environ.get("PFLBM_LIBRARY") or LIB_PATH
+def load(path: str = None, phase: str = "d3q15"):
+    """Load the build of the given phase lattice: libpflbm.so ("d3q15", or the
+    build named by $PFLBM_LIBRARY) or libpflbm_d3q27.so ("d3q27"); raises if
+    it is missing (there is no fallback path)."""
+    key = path or phase
+    if key in _libs:
+        return _libs[key]
+    if path is None:
+        path = (os.environ.get("PFLBM_LIBRARY") if phase == "d3q15" else None) or LIB_PATHS[phase]
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build it with `python -m paper_2206_11637_amd.build` "
@@ -82,8 +88,17 @@ def load(path: str = None):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    _lib = lib
+    _libs[key] = lib
     return lib
+
+
+def register(ctx, lib) -> None:
+    """Remember which build a context belongs to (for its error messages)."""
+    _ctx_lib[ctx.value] = lib
+
+
+def unregister(ctx) -> None:
+    _ctx_lib.pop(ctx.value, None)
 
 
 class PFLBMError(RuntimeError):
@@ -94,7 +109,7 @@ class PFLBMError(RuntimeError):
 
 def check(status: int, ctx=None, what: str = "") -> None:
     if status != PFLBM_OK:
-        lib = load()
+        lib = _ctx_lib.get(ctx.value if ctx is not None else None) or load()
         detail = lib.pflbm_last_error(ctx).decode() if ctx else ""
         base = lib.pflbm_status_string(status).decode()
         raise PFLBMError(status, f"{what}: {base}" + (f": {detail}" if detail else ""))

@@ -831,14 +831,16 @@ pflbm_status pflbm_sync(pflbm_ctx* c) {
 }
 
 pflbm_status pflbm_lattice(int32_t q, int32_t* c_out, double* w_out) {
-  if (q != 15 && q != 27) return PFLBM_ERR_ARG;
+  if (q != Q_H && q != Q_G) return PFLBM_ERR_ARG;
   for (int i = 0; i < q; ++i) {
-    const Dir d = q == 15 ? ch(i) : cg(i);
+    const Dir d = q == Q_H ? ch(i) : cg(i);
     if (c_out) { c_out[3 * i] = d.x; c_out[3 * i + 1] = d.y; c_out[3 * i + 2] = d.z; }
-    if (w_out) w_out[i] = q == 15 ? wh(i) : wg(i);
+    if (w_out) w_out[i] = q == Q_H ? wh(i) : wg(i);
   }
   return PFLBM_OK;
 }
+
+int32_t pflbm_phase_q(void) { return Q_H; }
 
 const char* pflbm_status_string(pflbm_status s) {
   switch (s) {

@@ -12,9 +12,10 @@ from . import _lib
 from ._lib import Desc, Params, check, load
 
 
-def lattice(q: int):
-    """(c [q,3] int array, w [q] float array) in the library's velocity order."""
-    lib = load()
+def lattice(q: int, phase: str = "d3q15"):
+    """(c [q,3] int array, w [q] float array) in the library's velocity order
+    (q = the build's phase-lattice size or 27)."""
+    lib = load(phase=phase)
     c = (C.c_int32 * (3 * q))()
     w = (C.c_double * q)()
     check(lib.pflbm_lattice(q, c, w), None, "pflbm_lattice")
@@ -50,10 +51,13 @@ class Simulation:
 
     def __init__(self, nx: int, ny: int, nz: int, periodic=(True, False, True),
                  precision: str = "fp32", collision: str = "mrt", solid=None, params=None,
-                 device: str = "cuda:0", streaming: str = "ab", forcing: str = "first"):
+                 device: str = "cuda:0", streaming: str = "ab", forcing: str = "first",
+                 phase_lattice: str = "d3q15"):
         self.streaming = streaming
         self.forcing = forcing
-        self.lib = load()
+        self.phase_lattice = phase_lattice
+        self.lib = load(phase=phase_lattice)
+        self.q_h = int(self.lib.pflbm_phase_q())
         self.device = torch.device(device)
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
@@ -72,6 +76,7 @@ class Simulation:
                                     C.c_void_p(self.stream.cuda_stream), C.byref(ctx)),
               None, "pflbm_create")
         self.ctx = ctx
+        _lib.register(ctx, self.lib)
         self._adj_ws = None
         if params is not None:
             self.set_params(params)
@@ -83,6 +88,7 @@ class Simulation:
     def __del__(self):
         try:
             if getattr(self, "ctx", None):
+                _lib.unregister(self.ctx)
                 self.lib.pflbm_destroy(self.ctx)
                 self.ctx = None
         except Exception:
@@ -134,7 +140,7 @@ class Simulation:
         return out
 
     def populations(self):
-        h = torch.empty((15, self.N), dtype=torch.float64, device=self.device)
+        h = torch.empty((self.q_h, self.N), dtype=torch.float64, device=self.device)
         g = torch.empty((27, self.N), dtype=torch.float64, device=self.device)
         check(self.lib.pflbm_read_populations(self.ctx, _ptr(h), _ptr(g)), self.ctx,
               "pflbm_read_populations")
@@ -209,11 +215,13 @@ class Simulation:
 
 
 def from_workload(wl, precision="fp32", collision="mrt", device="cuda:0", params=None,
-                  streaming="ab", forcing="first") -> Simulation:
+                  streaming="ab", forcing="first", phase_lattice="d3q15") -> Simulation:
     """Simulation for a workloads.Workload, initialised at equilibrium.
     streaming: "ab" (two buffers, fused step) or "aa" (in place);
-    forcing: "first" (first-order source) or "guo" (Guo's full source)."""
+    forcing: "first" (first-order source) or "guo" (Guo's full source);
+    phase_lattice: "d3q15" or "d3q27" (selects the library build)."""
     sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, precision, collision, wl.solid,
-                     params if params is not None else wl.params, device, streaming, forcing)
+                     params if params is not None else wl.params, device, streaming, forcing,
+                     phase_lattice)
     sim.init_equilibrium(wl.phi0, wl.u0, wl.pstar0)
     return sim

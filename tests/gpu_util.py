@@ -13,10 +13,11 @@ def say(msg):
     sys.stdout.flush()
 
 
-def perm_to_oracle(q):
-    """perm[j] = library index of oracle direction j."""
+def perm_to_oracle(q, phase="d3q15"):
+    """perm[j] = library index of oracle direction j (q = 15 or 27, in the
+    build of the given phase lattice)."""
     from paper_2206_11637_amd.sim import lattice
-    c_lib, _ = lattice(q)
+    c_lib, _ = lattice(q, phase)
     lat = OL.D3Q15 if q == 15 else OL.D3Q27
     pos = {tuple(v): i for i, v in enumerate(c_lib)}
     return np.array([pos[tuple(v)] for v in lat.c_np])
@@ -24,7 +25,7 @@ def perm_to_oracle(q):
 
 def gpu_pops_oracle_order(sim, to_cpu=True):
     h, g = sim.populations()
-    ph, pg = perm_to_oracle(15), perm_to_oracle(27)
+    ph, pg = perm_to_oracle(sim.q_h, sim.phase_lattice), perm_to_oracle(27, sim.phase_lattice)
     h = h[torch.as_tensor(ph, device=h.device)]
     g = g[torch.as_tensor(pg, device=g.device)]
     return (h.cpu(), g.cpu()) if to_cpu else (h, g)

@@ -106,6 +106,29 @@ def test_parameter_validation_without_a_gpu():
     assert lib.pflbm_destroy(ctx) == 0
 
 
+def test_d3q27_phase_build_loads_and_exports_every_symbol():
+    """The D3Q27-phase build is the same interface: every declared symbol,
+    pflbm_phase_q() = 27 (and 15 for the default build), its velocity set the
+    oracle's D3Q27, and 15 rejected as a lattice size."""
+    from oracle import lattice as OL
+    from paper_2206_11637_amd import _lib as L
+    from paper_2206_11637_amd.sim import lattice
+    if not os.path.exists(L.LIB_PATHS["d3q27"]):
+        pytest.skip("libpflbm_d3q27.so not built")
+    lib27 = L.load(phase="d3q27")
+    for name in declared_functions():
+        assert hasattr(lib27, name), name
+    assert lib27.pflbm_phase_q() == 27
+    assert L.load().pflbm_phase_q() == 15
+    c, w = lattice(27, "d3q27")
+    assert sorted(map(tuple, c)) == sorted(map(tuple, OL.D3Q27.c_np))
+    assert lib27.pflbm_lattice(15, None, None) == L.PFLBM_ERR_ARG
+    # 27 h per cell: the workspace grows by 12 populations per cell and buffer
+    d = L.Desc(8, 8, 8, 7, 1, 1, 0)
+    n15, n27 = L.load().pflbm_workspace_bytes(C.byref(d)), lib27.pflbm_workspace_bytes(C.byref(d))
+    assert n27 - n15 >= 2 * 12 * 4 * 512
+
+
 def test_library_velocity_sets_match_the_oracle_lattices():
     from oracle import lattice as OL
     from paper_2206_11637_amd.sim import lattice

@@ -8,19 +8,21 @@ from oracle import lattice as L
 from oracle import pflbm as P
 
 
-def _setup(wl, collision="mrt"):
+def _setup(wl, collision="mrt", phase="d3q15"):
     grid = P.Grid(wl.nx, wl.ny, wl.nz, wl.periodic, wl.solid)
-    prm = P.OracleParams.from_workload(wl.params, collision)
-    h, g = P.init_equilibrium(grid, wl.phi0, wl.u0, wl.pstar0)
+    prm = P.OracleParams.from_workload(wl.params, collision, phase_lattice=phase)
+    h, g = P.init_equilibrium(grid, wl.phi0, wl.u0, wl.pstar0, phase)
     return grid, prm, h, g
 
 
+@pytest.mark.parametrize("phase", ["d3q15", "d3q27"])
 @pytest.mark.parametrize("collision", ["bgk", "mrt"])
-def test_phase_mass_and_pressure_sum_conserved_with_walls_and_solids(collision):
+def test_phase_mass_and_pressure_sum_conserved_with_walls_and_solids(collision, phase):
     """Sum of phi and sum of p* over fluid cells are invariants of the step
-    (paper: the model is mass conserving); walls and solids included."""
+    (paper: the model is mass conserving); walls and solids included; both
+    phase lattices."""
     wl = W.random_state(11, 9, 7, periodic=(True, False, True), solid_fraction=0.1, seed=3)
-    grid, prm, h, g = _setup(wl, collision)
+    grid, prm, h, g = _setup(wl, collision, phase)
     r0 = P.reductions(grid, h, g)
     h, g = P.run(grid, prm, h, g, 60)
     r1 = P.reductions(grid, h, g)

@@ -14,11 +14,15 @@ from oracle import pflbm as P
 
 
 def _run(grid, prm, phi0, u0, p0, n):
-    h, g = P.init_equilibrium(grid, phi0, u0, p0)
+    h, g = P.init_equilibrium(grid, phi0, u0, p0, prm.phase_lattice)
     return P.run(grid, prm, h, g, n)
 
 
-def test_phase_field_diffuses_at_the_mobility():
+PHASE = pytest.mark.parametrize("phase", ["d3q15", "d3q27"])
+
+
+@PHASE
+def test_phase_field_diffuses_at_the_mobility(phase):
     """xi = inf switches the counter-term off and u stays 0: the h-LBE is pure
     diffusion with coefficient M, so a Fourier mode decays as exp(-M k^2 t).
     Pins omega_phi = 1/(3M + 1/2) (paper eq. pflbm-tau)."""
@@ -26,14 +30,15 @@ def test_phase_field_diffuses_at_the_mobility():
     grid = P.Grid(nx, 1, 1, (True, True, True))
     x = np.arange(nx) + 0.5
     k = 2 * math.pi / nx
-    prm = P.OracleParams(0.8, 0.8, M, math.inf, 0.0, 1.0, 1.0, (0, 0, 0))
+    prm = P.OracleParams(0.8, 0.8, M, math.inf, 0.0, 1.0, 1.0, (0, 0, 0), phase_lattice=phase)
     h, _ = _run(grid, prm, 0.5 + 1e-3 * np.sin(k * x), np.zeros((3, nx)), np.zeros(nx), n)
     amp = 2 * np.sum((h.sum(0).numpy() - 0.5) * np.sin(k * x)) / nx
     rate = -math.log(amp / 1e-3) / n
     assert abs(rate / (M * k * k) - 1) < 0.01
 
 
-def test_interface_advected_by_uniform_flow():
+@PHASE
+def test_interface_advected_by_uniform_flow(phase):
     """Uniform u, no forces: the phase field translates by u t (pins the c.u
     term of the phase-field equilibrium)."""
     nx, U, n = 64, 0.02, 800
@@ -42,7 +47,7 @@ def test_interface_advected_by_uniform_flow():
     phi0 = 0.5 + 0.5 * np.tanh(2 * np.minimum(x - 16, 48 - x) / 4)
     u0 = np.zeros((3, nx))
     u0[0] = U
-    prm = P.OracleParams(0.8, 0.8, 0.02, 4.0, 0.0, 1.0, 1.0, (0, 0, 0))
+    prm = P.OracleParams(0.8, 0.8, 0.02, 4.0, 0.0, 1.0, 1.0, (0, 0, 0), phase_lattice=phase)
     h, _ = _run(grid, prm, phi0, u0, np.zeros(nx), n)
 
     def centre(p):
@@ -52,7 +57,8 @@ def test_interface_advected_by_uniform_flow():
     assert abs(shift - U * n) < 1e-3
 
 
-def test_flat_interface_is_stationary_with_width_xi():
+@PHASE
+def test_flat_interface_is_stationary_with_width_xi(phase):
     """A flat tanh interface at rest stays put, and the discrete equilibrium
     profile keeps width xi.  Pins the counter-term factor 4 phi(1-phi)/xi and
     its first moment c_s^2 theta n (a factor-3 error would sharpen it 3x)."""
@@ -60,7 +66,7 @@ def test_flat_interface_is_stationary_with_width_xi():
     grid = P.Grid(1, ny, 1, (True, False, True))
     y = np.arange(ny) + 0.5
     phi0 = 0.5 + 0.5 * np.tanh(2 * (16 - y) / xi)
-    prm = P.OracleParams(0.53, 0.53, 0.02, xi, 1e-4, 1.0, 1e-3, (0, 0, 0))
+    prm = P.OracleParams(0.53, 0.53, 0.02, xi, 1e-4, 1.0, 1e-3, (0, 0, 0), phase_lattice=phase)
     h, g = _run(grid, prm, phi0, np.zeros((3, ny)), np.zeros(ny), 2000)
     phi = h.sum(0).numpy()
     assert abs(P.interface_crossing(phi, 16.0) - 16.0) < 1e-4
@@ -110,7 +116,8 @@ def test_two_layer_channel_flow_matches_variable_viscosity_ode():
 
 
 @pytest.mark.slow
-def test_laplace_pressure_of_a_static_drop():
+@PHASE
+def test_laplace_pressure_of_a_static_drop(phase):
     """Heavy drop (R = 7) in a light phase (density ratio 1000): the pressure
     p = p* rho c_s^2 jumps by 2 sigma / R.  Pins beta = 12 sigma/xi,
     kappa = 3 sigma xi / 2, F_s = mu_phi grad phi and the sign of F_p."""
@@ -118,7 +125,7 @@ def test_laplace_pressure_of_a_static_drop():
     grid = P.Grid(n, n, n, (True, True, True))
     z, y, x = np.meshgrid(*(np.arange(n) + 0.5,) * 3, indexing="ij")
     r = np.sqrt((x - n / 2) ** 2 + (y - n / 2) ** 2 + (z - n / 2) ** 2)
-    prm = P.OracleParams(0.8, 0.8, 0.05, xi, sigma, 1.0, rL, (0, 0, 0))
+    prm = P.OracleParams(0.8, 0.8, 0.05, xi, sigma, 1.0, rL, (0, 0, 0), phase_lattice=phase)
     h, g = _run(grid, prm, 0.5 + 0.5 * np.tanh(2 * (R - r) / xi), np.zeros((3, n, n, n)),
                 np.zeros((n, n, n)), 800)
     phi, u, ps = P.moments(grid, prm, h, g)
