@@ -66,9 +66,26 @@ if ROOT not in sys.path:
 
 import workloads as W  # noqa: E402
 
-BO, MO, RHO_RATIO, MU_RATIO = 100.0, 0.015, 744.0, 4236.0
-OMEGA_H, MOBILITY, XI = 1.76, 0.08, 3.0
-RE_PAPER = {64: 26.83, 128: 27.12}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "taylor_bubble.txt")
+
+
+def golden(path: str = GOLDEN) -> dict:
+    """The paper's printed setup and Re values (tests/golden/taylor_bubble.txt)."""
+    out = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        k, v = (s.strip() for s in line.split("=", 1))
+        vals = [float(t) for t in v.split()]
+        out[k] = vals[0] if len(vals) == 1 else vals
+    return out
+
+
+_G = golden()
+BO, MO, RHO_RATIO, MU_RATIO = _G["Bo"], _G["Mo"], _G["density_ratio"], _G["viscosity_ratio"]
+OMEGA_H, MOBILITY, XI = _G["omega_H"], _G["mobility"], _G["xi"]
+RE_PAPER = {64: _G["Re_PFLBM_D64"], 128: _G["Re_PFLBM_D128"]}
 
 
 @dataclasses.dataclass(frozen=True)
@@ -100,19 +117,23 @@ def constants(D: int) -> Constants:
 def setup(D: int, gauge: str = "mid", s_bulk: float = 1.0):
     """Workload of one Taylor-bubble run and its constants."""
     c = constants(D)
-    nx, ny, nz = D, 10 * D, D
+    lx, ly, lz = (int(round(v * D)) for v in _G["domain"])     # the paper's x, y, z
+    nx, ny, nz = lx, lz, ly                                    # its tube axis z is our y
     z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5,
                           indexing="ij")
     rr = np.sqrt((x - 0.5 * D) ** 2 + (z - 0.5 * D) ** 2)
     solid = rr > 0.5 * D
-    R, y0, y1 = 0.375 * D, 1.0 * D, 4.0 * D
+    R = 0.5 * _G["bubble_diameter"] * D
+    y0 = _G["bubble_bottom"] * D
+    y1 = y0 + _G["bubble_length"] * D
     dist = np.maximum(np.maximum(rr - R, y0 - y), y - y1)      # > 0 outside the gas
     phi0 = W.tanh_profile(dist, XI)
     del rr, x, z
     ymid = 0.5 * (y0 + y1)
     if gauge == "paper":
-        p_liq = 1.0 / 3.0 + c.g * (5.0 * D - y)
-        p_gas = 1.0 / 3.0 + c.g * (5.0 * D - ymid)
+        yref = _G["reference_pressure_height"] * D
+        p_liq = 1.0 / 3.0 + c.g * (yref - y)
+        p_gas = 1.0 / 3.0 + c.g * (yref - ymid)
     elif gauge == "mid":
         p_liq = c.g * (ymid - y)
         p_gas = 0.0

@@ -43,14 +43,35 @@ import workloads as W  # noqa: E402
 from oracle import analytic as A  # noqa: E402
 from oracle.pflbm import interface_crossing  # noqa: E402
 
-RE, RHO_H, RHO_L, OMEGA_H, MOBILITY, XI = 10.0, 1.0, 1e-3, 1.99, 0.02, 5.0
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "standing_waves.txt")
+
+
+def golden(path: str = GOLDEN) -> dict:
+    """The paper's printed wave setup (tests/golden/standing_waves.txt)."""
+    out = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        k, v = (s.strip() for s in line.split("=", 1))
+        vals = [float(t) for t in v.split()]
+        out[k] = vals[0] if len(vals) == 1 else vals
+    return out
+
+
+_G = golden()
+RE, OMEGA_H, MOBILITY, XI = _G["Re"], _G["omega_H"], _G["mobility"], _G["xi"]
+RHO_H = 1.0
+RHO_L = RHO_H / _G["density_ratio"]
+DT_STAR = _G["sample_every_t_star"]
+assert _G["kinematic_viscosity_ratio"] == 1.0    # one tau for both phases below
 
 
 def setup(kind: str, L: int):
     """Workload and constants of one standing-wave run."""
     tau = 1.0 / OMEGA_H
     nu = (tau - 0.5) / 3.0
-    a0, d, k = 0.01 * L, 0.5 * L, 2.0 * math.pi / L
+    a0, d, k = _G["amplitude"] * L, _G["depth"] * L, 2.0 * math.pi / L
     w0 = RE * nu / (a0 * L)
     if kind == "capillary":
         sigma, g = w0 ** 2 * (RHO_H + RHO_L) / k ** 3, 0.0
@@ -87,8 +108,8 @@ def run(kind: str, L: int, tmax: float, precision: str = "fp32", streaming: str 
     wl, c = setup(kind, L)
     sim = from_workload(wl, precision=precision, collision="mrt", streaming=streaming)
     m0 = sim.reduce()[0]
-    every = 0.1 / c["w0"]
-    nsamp = int(round(tmax / 0.1))
+    every = DT_STAR / c["w0"]
+    nsamp = int(round(tmax / DT_STAR))
     steps = [int(round(i * every)) for i in range(nsamp + 1)]
     ac, asum, done, t0 = [], [], 0, time.time()
     for i, s in enumerate(steps):
@@ -98,7 +119,7 @@ def run(kind: str, L: int, tmax: float, precision: str = "fp32", streaming: str 
         ac.append((interface_crossing(col, c["d"]) - c["d"]) / c["a0"])
         asum.append((col.sum() - c["d"]) / c["a0"])
         if log and (i % 100 == 0 or i == nsamp):
-            log(f"  {kind} L={L}: t*={i * 0.1:5.1f} step {s} a*={ac[-1]:+.4f} "
+            log(f"  {kind} L={L}: t*={i * DT_STAR:5.1f} step {s} a*={ac[-1]:+.4f} "
                 f"({time.time() - t0:.0f} s)")
     mass_drift = float((sim.reduce()[0] - m0) / m0)
     torch.cuda.synchronize()
@@ -138,8 +159,8 @@ def summary(tstar, a, ref):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--L", type=int, nargs="+", default=[50, 100, 200, 400])
-    ap.add_argument("--tmax", type=float, default=80.0)
+    ap.add_argument("--L", type=int, nargs="+", default=[int(v) for v in _G["L"]])
+    ap.add_argument("--tmax", type=float, default=_G["t_star_max"])
     ap.add_argument("--tmax-large", type=float, default=None,
                     help="t* limit for L >= 400 (default: --tmax)")
     ap.add_argument("--kinds", nargs="+", default=["gravity", "capillary"])
