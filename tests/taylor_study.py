@@ -158,7 +158,8 @@ def reynolds(c: Constants, y10: float, y15: float) -> float:
 
 
 def run(D: int, precision: str = "fp64", gauge: str = "mid", streaming: str = "ab",
-        tmax: float = 15.0, s_bulk: float = 1.0, every: float = 0.5, log=None):
+        tmax: float = 15.0, s_bulk: float = 1.0, every: float = 0.5, log=None,
+        phase_lattice: str = "d3q15"):
     """Simulate to t* = tmax, sampling the centre of mass every `every` of t*.
 
     Re is the paper's (t* = 10 to 15) when the run reaches t* = 15; a run that
@@ -170,7 +171,8 @@ def run(D: int, precision: str = "fp64", gauge: str = "mid", streaming: str = "a
     wl, c = setup(D, gauge, s_bulk)
     fluid = torch.as_tensor(~wl.solid, device="cuda:0")
     yy = (torch.arange(wl.ny, dtype=torch.float64, device="cuda:0") + 0.5).view(1, wl.ny, 1)
-    sim = from_workload(wl, precision=precision, collision="mrt", streaming=streaming)
+    sim = from_workload(wl, precision=precision, collision="mrt", streaming=streaming,
+                        phase_lattice=phase_lattice)
     del wl.phi0, wl.pstar0, wl.u0
 
     def centre(phi):
@@ -204,6 +206,7 @@ def run(D: int, precision: str = "fp64", gauge: str = "mid", streaming: str = "a
                 f"gas volume {vol:10.1f} ({time.time() - t0:.0f} s)")
     torch.cuda.synchronize()
     out = dict(D=D, precision=precision, gauge=gauge, streaming=streaming, s_bulk=s_bulk,
+               phase_lattice=phase_lattice,
                g=c.g, sigma=c.sigma,
                tau_H=c.tau_H, tau_L=c.tau_L, t_ref=c.t_ref, steps=done, finite=finite,
                tstar=ts, centre=ys, gas_volume=vols, seconds=time.time() - t0,
@@ -229,6 +232,7 @@ def main():
     ap.add_argument("--s-bulk", type=float, default=1.0)
     ap.add_argument("--tmax", type=float, default=15.0)
     ap.add_argument("--every", type=float, default=0.5)
+    ap.add_argument("--phase-lattice", default="d3q15", choices=["d3q15", "d3q27"])
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
 
@@ -239,9 +243,10 @@ def main():
     for D in args.D:
         for prec in args.precision:
             for gauge in args.gauge:
-                log(f"Taylor bubble D={D} {prec} gauge={gauge} s_bulk={args.s_bulk}")
+                log(f"Taylor bubble D={D} {prec} gauge={gauge} s_bulk={args.s_bulk} "
+                    f"phase lattice {args.phase_lattice}")
                 r = run(D, prec, gauge, tmax=args.tmax, s_bulk=args.s_bulk, every=args.every,
-                        log=log)
+                        log=log, phase_lattice=args.phase_lattice)
                 if "Re" in r:
                     what = f"Re(t* 10-15) = {r['Re']:.3f}"
                 elif "Re_last" in r:
