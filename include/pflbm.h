@@ -97,7 +97,7 @@ typedef struct {
   int32_t collision;      /* pflbm_collision                                      */
   int32_t has_mask;       /* 1: pflbm_set_mask must be called before init          */
   int32_t streaming;      /* pflbm_streaming                                      */
-  int32_t forcing;        /* pflbm_forcing (the reverse mode: FIRST only)          */
+  int32_t forcing;        /* pflbm_forcing                                        */
 } pflbm_desc;
 
 typedef struct {

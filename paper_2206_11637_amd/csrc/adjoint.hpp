@@ -68,8 +68,8 @@ __device__ __forceinline__ R second_moment_t(Dir d, const Sym<R>& L) {
 // adjoints of the post-collision populations, out = adjoints of the
 // pre-collision ones (the cell-local part).  Outputs the adjoints of the
 // stencil inputs (grad phi, lap phi) and of omega_phi and sigma.  BULK: the
-// bulk mode of g relaxes at P.s_bulk (MRT only).
-template <typename R, bool MRT, bool BULK>
+// bulk mode of g relaxes at P.s_bulk (MRT only); GUO: Guo's full source.
+template <typename R, bool MRT, bool BULK, bool GUO>
 __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R Gx, R Gy, R Gz,
                                          R lap, const Phys<R>& P, const AdjConst<R>& K,
                                          R (&lh)[Q_H], R (&lg)[Q_G], R& lGx, R& lGy, R& lGz,
@@ -219,11 +219,13 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   R la1x = R(0), la1y = R(0), la1z = R(0);
   Sym<R> lA2{R(0), R(0), R(0), R(0), R(0), R(0)};
   R Lb = R(0);   // sum_i lambda_i w_i (|c_i|^2 - 1): adjoint of the bulk-mode term
+  Sym<R> LG2{R(0), R(0), R(0), R(0), R(0), R(0)};   // d/dS of sum_i lambda_i 4.5 w_i H2(c_i):S
   {  // rest population
     const R w = R(wg(0));
     const R lam = lg[0];
     l_base += s * lam * w;
     if constexpr (BULK) Lb -= lam * w;
+    if constexpr (GUO) hermite2_grad(cg(0), R(4.5) * lam * w, LG2);
     if (MRT) {
       hermite2_grad(cg(0), R(4.5) * dlo * lam * w, lA2);
       lom += lam * w * R(4.5) * hermite2(cg(0), A2);
@@ -240,6 +242,7 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
     const R cu = dot(d, ux, uy, uz);
     l_base += s * w * sp;
     if constexpr (BULK) Lb += R(d.x * d.x + d.y * d.y + d.z * d.z - 1) * w * sp;
+    if constexpr (GUO) hermite2_grad(d, R(4.5) * w * sp, LG2);
     const R lcu = s * w * (R(3) * sm + R(9) * cu * sp);
     if (d.x) lux += d.x > 0 ? lcu : -lcu;
     if (d.y) luy += d.y > 0 ? lcu : -lcu;
@@ -273,6 +276,34 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   }
   lom += l_fk * (-R(1.5) / rho);
   R l_rho = -l_fk * fk / rho;
+  if constexpr (GUO) {
+    // g*_i += 4.5 w_i kf H2(c_i):S, kf = (1 - omega/2)/rho, S = u F^T + F u^T
+    const R kf = (R(1) - R(0.5) * om) / rho;
+    const R Sxx = R(2) * ux * Fx, Syy = R(2) * uy * Fy, Szz = R(2) * uz * Fz;
+    const R Sxy = ux * Fy + uy * Fx, Sxz = ux * Fz + uz * Fx, Syz = uy * Fz + uz * Fy;
+    const R LS = LG2.xx * Sxx + LG2.yy * Syy + LG2.zz * Szz + LG2.xy * Sxy + LG2.xz * Sxz +
+                 LG2.yz * Syz;
+    lom -= LS / (R(2) * rho);
+    l_rho -= LS * kf / rho;
+    lux += kf * (R(2) * LG2.xx * Fx + LG2.xy * Fy + LG2.xz * Fz);
+    luy += kf * (LG2.xy * Fx + R(2) * LG2.yy * Fy + LG2.yz * Fz);
+    luz += kf * (LG2.xz * Fx + LG2.yz * Fy + R(2) * LG2.zz * Fz);
+    lFx += kf * (R(2) * LG2.xx * ux + LG2.xy * uy + LG2.xz * uz);
+    lFy += kf * (LG2.xy * ux + R(2) * LG2.yy * uy + LG2.yz * uz);
+    lFz += kf * (LG2.xz * ux + LG2.yz * uy + R(2) * LG2.zz * uz);
+    if constexpr (MRT && BULK) {
+      // its trace with (1 - s_bulk/2): g*_i += 4.5 w_i (|c_i|^2 - 1) kd,
+      // kd = (omega - s_bulk) tr(S) / (6 rho), tr(S) = 2 u.F
+      const R trS = Sxx + Syy + Szz;
+      const R kd = (om - P.s_bulk) * trS / (R(6) * rho);
+      const R l_kd = R(4.5) * Lb;
+      lom += l_kd * trS / (R(6) * rho);
+      l_rho -= l_kd * kd / rho;
+      const R ltr = R(2) * l_kd * (om - P.s_bulk) / (R(6) * rho);
+      lux += ltr * Fx; luy += ltr * Fy; luz += ltr * Fz;
+      lFx += ltr * ux; lFy += ltr * uy; lFz += ltr * uz;
+    }
+  }
   R l_p = l_base;
   l_uu += -R(1.5) * l_base;
   R ljx = R(0), ljy = R(0), ljz = R(0);
@@ -404,7 +435,7 @@ struct AdjArgs {
 template <typename S>
 struct AdjWaves { static constexpr int value = sizeof(S) == 8 ? 1 : PFLBM_ADJ_WAVES; };
 
-template <typename S, bool MRT, int RULE, bool MASK, bool BULK>
+template <typename S, bool MRT, int RULE, bool MASK, bool BULK, bool GUO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjWaves<S>::value)))
 void k_adj_cell(AdjArgs<S> a) {
   using St = Store<S>;
@@ -457,7 +488,7 @@ void k_adj_cell(AdjArgs<S> a) {
       lg[i] = *reinterpret_cast<const R*>(pair_base(a.lg_in, G.N, i) + off);
     }
     R lGx, lGy, lGz, lL, lomp, lsig;
-    cell_vjp<R, MRT, BULK>(h, g, Gx, Gy, Gz, lap, a.P, a.K, lh, lg, lGx, lGy, lGz, lL, lomp, lsig);
+    cell_vjp<R, MRT, BULK, GUO>(h, g, Gx, Gy, Gz, lap, a.P, a.K, lh, lg, lGx, lGy, lGz, lL, lomp, lsig);
 #pragma unroll
     for (int i = 0; i < Q_H; ++i) *slot(a.lh_out, G.N, i, idx) = lh[i];
 #pragma unroll

@@ -16,11 +16,11 @@ pytestmark = pytest.mark.gpu
 
 
 def _gpu_grads(wl, precision, collision, nsteps, K, depth, target, ckpt=None, M=None, sigma=None,
-               stats=None, streaming="ab"):
+               stats=None, streaming="ab", forcing="first"):
     from paper_2206_11637_amd.rollout import amplitude_rollout
     from paper_2206_11637_amd.sim import Simulation
     sim = Simulation(wl.nx, wl.ny, wl.nz, wl.periodic, precision, collision, wl.solid, wl.params,
-                     streaming=streaming)
+                     streaming=streaming, forcing=forcing)
     dev = sim.device
     phi0 = torch.tensor(wl.phi0, dtype=torch.float64, device=dev, requires_grad=True)
     Mt = torch.tensor(M if M is not None else wl.params.mobility, dtype=torch.float64, device=dev,
@@ -68,15 +68,26 @@ def test_fp64_adjoint_with_a_bulk_rate_matches_oracle_autograd(s_bulk, solids, n
     _adjoint_vs_oracle(wl, "mrt", nsteps, ckpt)
 
 
-def _adjoint_vs_oracle(wl, collision, nsteps, ckpt):
+@pytest.mark.parametrize("collision,s_bulk", [("mrt", 0.0), ("bgk", 0.0), ("mrt", 1.3)])
+def test_fp64_adjoint_with_guos_full_source_matches_oracle_autograd(collision, s_bulk):
+    """The reverse step with Guo's full source (forcing="guo"), also with a
+    bulk rate."""
+    wl = _small(collision, True)
+    wl = dataclasses.replace(wl, params=wl.params.copy(s_bulk=s_bulk))
+    say(f"case: adjoint fp64 guo {collision} s_bulk={s_bulk} N=23 ckpt=4")
+    _adjoint_vs_oracle(wl, collision, 23, 4, forcing="guo")
+
+
+def _adjoint_vs_oracle(wl, collision, nsteps, ckpt, forcing="first"):
     K = 3 if nsteps % 3 == 0 else 1
     rng = np.random.default_rng(5)
     target = rng.normal(0, 0.05, nsteps // K)
     grid = OP.Grid(wl.nx, wl.ny, wl.nz, wl.periodic, wl.solid)
-    prm = OP.OracleParams.from_workload(wl.params, collision)
+    prm = OP.OracleParams.from_workload(wl.params, collision, forcing)
     Lo, dphio, dMo, dso, tro = AD.loss_and_gradients(grid, prm, wl.phi0, wl.u0, wl.pstar0, nsteps,
                                                      K, 12.0, target)
-    Lg, dphig, dMg, dsg, trg = _gpu_grads(wl, "fp64", collision, nsteps, K, 12.0, target, ckpt)
+    Lg, dphig, dMg, dsg, trg = _gpu_grads(wl, "fp64", collision, nsteps, K, 12.0, target, ckpt,
+                                          forcing=forcing)
     e_tr = (trg - tro).abs().max().item()
     e_phi = (dphig - dphio).abs().max().item() / dphio.abs().max().item()
     # conditioning floor of dL/dphi0: the oracle's own gradient under a 1e-15
@@ -208,16 +219,3 @@ def test_in_place_scheme_gives_the_same_gradients(precision, tol):
     say(f"  L {_rel(Lb, La):.1e} dM {_rel(Mb, Ma):.1e} dsigma {_rel(sb, sa):.1e} dphi0 {e_phi:.1e}")
     assert _rel(Lb, La) <= tol and _rel(Mb, Ma) <= tol and _rel(sb, sa) <= tol and e_phi <= tol
 
-
-def test_reverse_mode_refuses_guos_full_source():
-    """The reverse step is derived for the first-order source: a context with
-    Guo's full source is refused rather than differentiated wrongly."""
-    from paper_2206_11637_amd._lib import PFLBMError
-    from paper_2206_11637_amd.sim import from_workload
-    wl = _small("mrt", False)
-    say("case: adjoint with forcing=guo (refused)")
-    sim = from_workload(wl, precision="fp64", forcing="guo")
-    state = sim.save_state()
-    sim.adjoint_attach()
-    with pytest.raises(PFLBMError, match="first-order source"):
-        sim.adjoint_step(state, 0)
