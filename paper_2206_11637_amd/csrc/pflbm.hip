@@ -59,6 +59,11 @@ struct Layout {
 #ifndef PFLBM_TILE_X
 #define PFLBM_TILE_X 64
 #endif
+// each thread of a 256-thread block derives at most one cell of the tile's
+// one-cell ring, 2 (bx + 2) + 2 by cells
+static_assert(PFLBM_TILE_X >= 16 && PFLBM_TILE_X <= 64 && 256 % PFLBM_TILE_X == 0 &&
+                  2 * (PFLBM_TILE_X + 2) + 2 * (256 / PFLBM_TILE_X) <= 256,
+              "unsupported tile width");
 #ifndef PFLBM_STEP_BLOCKS
 #define PFLBM_STEP_BLOCKS 2048
 #endif
