@@ -59,6 +59,9 @@ RAGGED = [
     (17, 33, 5, (True, True, True), 0.0, 6),
     (1, 24, 1, (True, False, True), 0.0, 9),
     (40, 3, 1, (True, True, True), 0.0, 4),
+    # several tiles in x and y, interior ones included
+    (200, 20, 12, (True, False, True), 0.0, 5),
+    (200, 20, 12, (False, False, False), 0.0, 5),
 ]
 
 
@@ -173,6 +176,25 @@ def test_full_guo_source_in_reduced_precision(precision, tol_phi):
     dphi = (sim.phi() - ref.phi()).abs().max().item()
     say(f"  {precision}: max|dphi|={dphi:.2e}")
     assert dphi <= tol_phi
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16s"])
+@pytest.mark.parametrize("periodic", [(True, False, True), (False, False, False)])
+def test_an_all_fluid_mask_changes_nothing_bitwise(precision, periodic):
+    """The masked kernel variants (solid neighbour bits read per cell) with a
+    mask that marks no solid give bit for bit the results of the unmasked
+    variants, on a lattice of several tiles in x and y."""
+    wl = W.random_state(264, 28, 13, periodic=periodic, solid_fraction=0.0, seed=8, steps=7)
+    say(f"case: all-fluid mask vs no mask {precision} periodic={periodic}")
+    a = _sim(wl, precision)
+    b = _sim(dataclasses.replace(wl, solid=np.zeros((wl.nz, wl.ny, wl.nx), dtype=bool)),
+             precision)
+    a.step(wl.steps)
+    b.step(wl.steps)
+    ha, ga = a.populations()
+    hb, gb = b.populations()
+    assert torch.equal(ha, hb) and torch.equal(ga, gb)
+    assert torch.equal(a.phi(), b.phi())
 
 
 @pytest.mark.parametrize("streaming", STREAMING)
