@@ -39,7 +39,7 @@ STEP_BYTES_D3Q27 = {"fp64": 880, "fp32": 440, "fp16s": 224}
 # gives on the same box (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE); taken for
 # the current kernel (profiles/k_step_rising_bubble_128x512x128_hbm_traffic.txt)
 # and to be re-measured whenever it changes
-TRAFFIC = {"fp32": 3.404e9, "fp16s": 1.558e9, "fp64": 6.037e9}
+TRAFFIC = {"fp32": 3.405e9, "fp16s": 1.558e9, "fp64": 6.038e9}
 
 
 def log(msg):
