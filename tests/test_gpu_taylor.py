@@ -5,9 +5,9 @@ PFLBM at that resolution (26.83).  Setup and readings in tests/taylor_study.py.
 At D = 64 the run here turns non-finite between t* = 14 and 15 (the gas,
 with a kinematic viscosity of 0.004 lattice units and a 744:1 density ratio,
 circulates at up to ~0.1 inside the bubble), so the test measures the rise
-velocity over t* = 10 to 14, where the rise is already steady; the paper's
-window t* = 10 to 15 is met at D = 128 by the study script (Re 26.96 against
-the paper's 27.12, FP32)."""
+velocity over t* = 10 to 14, where the rise is already steady (Re 26.20 from
+the gas region's centre of mass); the paper's window t* = 10 to 15 is met at
+D = 128 by the study script (Re 26.55 against the paper's 27.12, FP32)."""
 import pytest
 
 from gpu_util import say
