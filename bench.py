@@ -256,8 +256,8 @@ def main():
                     help="only run a plain device copy of 2 GiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU slab "
-              "decomposition is a design, not an implementation); use --gpus 1",
+        print("bench.py: the library runs on one GPU (the multi-GPU slab "
+              "decomposition is designed, not implemented); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -231,7 +231,7 @@ pflbm_status pflbm_sync(pflbm_ctx* ctx);
  * weights.  Either may be NULL. */
 pflbm_status pflbm_lattice(int32_t q, int32_t* c_out, double* w_out);
 
-/* Velocity count of this build's phase lattice: 15 (D3Q15, libpflbm.so) or
+/* Velocity count of this library's phase lattice: 15 (D3Q15, libpflbm.so) or
  * 27 (D3Q27, the velocity set the paper uses for both lattices in 3D:
  * libpflbm_d3q27.so, the same interface built with PFLBM_PHASE_D3Q27).  Every
  * "[15][N]" phase-field array of this interface has pflbm_phase_q() rows. */

@@ -14,7 +14,7 @@ from ._lib import Desc, Params, check, load
 
 def lattice(q: int, phase: str = "d3q15"):
     """(c [q,3] int array, w [q] float array) in the library's velocity order
-    (q = the build's phase-lattice size or 27)."""
+    (q = the loaded library's phase-lattice size or 27)."""
     lib = load(phase=phase)
     c = (C.c_int32 * (3 * q))()
     w = (C.c_double * q)()

@@ -1,0 +1,27 @@
+"""The benchmark's command line on the CPU: more than one GPU is refused with a
+message and a non-zero status before anything touches a GPU; the algorithmic
+byte counts it prices the roofline with follow from the population counts."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, cwd=ROOT, timeout=120,
+                       env=dict(os.environ, CUDA_VISIBLE_DEVICES=""))
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "--gpus 1" in (r.stdout + r.stderr)
+
+
+def test_algorithmic_bytes_per_cell():
+    sys.path.insert(0, ROOT)
+    import bench as B
+    for prec, s in (("fp64", 8), ("fp32", 4), ("fp16s", 2)):
+        phi = 4 if prec != "fp64" else 8
+        # populations read and written once, phi read (shift reference) and written once
+        assert B.STEP_BYTES[prec] == 2 * (15 + 27) * s + 2 * phi
+        assert B.STEP_BYTES_D3Q27[prec] == 2 * (27 + 27) * s + 2 * phi
+        assert B.AA_CELL_KERNEL_BYTES[prec] == 2 * (15 + 27) * s + phi
