@@ -48,6 +48,8 @@ def _tiled(wl, reps):
                                                  ("fp16s", (1024, 512, 1023), (32, 16, 31))])
 def test_lattice_at_the_offset_limit_evolves_like_its_tile(precision, dims, TILE):
     from paper_2206_11637_amd.sim import from_workload
+    gc.collect()
+    torch.cuda.empty_cache()          # earlier tests' cached blocks: room for ~190 GiB
     nx, ny, nz = dims
     N = nx * ny * nz
     per_cell = 8 if precision == "fp64" else 4
