@@ -113,8 +113,10 @@ typedef struct {
   double s_high;          /* MRT rate of moments of degree >= 3 (0 < s < 2)        */
   double fp16_scale_log2[2]; /* FP16S storage exponents k for h and g (integers,
                              |k| <= 24); ignored by the other precisions          */
-  double normal_eps;      /* > 0: n = grad phi / sqrt(|grad phi|^2 + eps^2); 1e-4 is
-                             the reference choice (see the design notes)          */
+  double normal_eps;      /* > 0: n = grad phi / sqrt(|grad phi|^2 + eps^2).  The
+                             paper leaves n undefined where grad phi = 0; 1e-4
+                             only touches cells many widths from an interface and
+                             keeps the reverse mode well conditioned              */
   double s_bulk;          /* MRT rate of the bulk mode of g (the trace of its
                              second-order moments, polynomial |c|^2 - 1): 0 = the
                              second-order rate omega(phi) (default), else in (0, 2).
@@ -125,7 +127,10 @@ typedef struct {
 /* Bytes of device workspace for a context with this description (256-aligned
  * regions: one (AA) or two (AB) population buffers, two phi buffers, the mask
  * and its neighbour bits, reduction partials).  Returns 0 if the description
- * is invalid. */
+ * is invalid: an enum out of range, an axis < 1, N = nx ny nz >= 2^29 (FP32
+ * and FP16 storage) or >= 2^28 (FP64) -- the population offsets within one
+ * opposite pair are 32-bit byte offsets -- or a shape so thin that its tiles
+ * (16-64 cells wide, 256 cells each) times nz reach 2^24 blocks. */
 size_t pflbm_workspace_bytes(const pflbm_desc* desc);
 
 /* Creates a host-side context that uses d_workspace (>= pflbm_workspace_bytes,

@@ -26,32 +26,6 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 size_t store_size(int precision) { return precision == PFLBM_FP64 ? 8 : precision == PFLBM_FP32 ? 4 : 2; }
 size_t real_size(int precision) { return precision == PFLBM_FP64 ? 8 : 4; }
 
-bool desc_ok(const pflbm_desc* d) {
-  if (!d) return false;
-  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return false;
-  if (d->precision < 0 || d->precision > 2) return false;
-  if (d->collision < 0 || d->collision > 1) return false;
-  if (d->periodic > 7u) return false;
-  if (d->streaming < 0 || d->streaming > 1) return false;
-  if (d->forcing < 0 || d->forcing > 1) return false;
-  const long long N = (long long)d->nx * d->ny * d->nz;
-  // population addressing uses 32-bit byte offsets within each opposite pair
-  // of populations (and within the FP32/FP64 adjoint arrays of one population)
-  const long long per_pair = 2 * N * (long long)(d->precision == PFLBM_FP64 ? 8 : 4);
-  if (per_pair >= (1ll << 32)) return false;
-  return true;
-}
-
-struct Layout {
-  int bx, by, tiles_x, tiles_y;
-  int zc, nchunks;          // z-chunks of the marching step kernel
-  unsigned nblocks;         // one-plane kernels: tiles x nz
-  unsigned nblocks_step;    // step kernel: tiles x nchunks
-  long long N;
-  size_t off_h[2], off_g[2], off_phi[2], off_mask, off_nbr, off_part, off_red, total;
-  size_t bytes_h, bytes_g, bytes_phi;
-};
-
 // Tile width of the one-thread-per-cell kernels (bx * by = 256) and the
 // number of blocks the step kernel aims for when it splits z into chunks
 // (each chunk re-derives two extra phi planes, so fewer, longer chunks cost
@@ -71,10 +45,50 @@ static_assert(PFLBM_TILE_X >= 16 && PFLBM_TILE_X <= 64 && 256 % PFLBM_TILE_X == 
 #define PFLBM_MIN_ZC 4
 #endif
 
+// Tile of the one-thread-per-cell kernels (bx * by = 256); narrow grids use
+// narrower tiles.
+void tile_shape(int nx, int& bx, int& by) {
+  bx = nx > 32 ? PFLBM_TILE_X : (nx > 16 ? 32 : 16);
+  by = 256 / bx;
+}
+
+bool desc_ok(const pflbm_desc* d) {
+  if (!d) return false;
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return false;
+  if (d->precision < 0 || d->precision > 2) return false;
+  if (d->collision < 0 || d->collision > 1) return false;
+  if (d->periodic > 7u) return false;
+  if (d->streaming < 0 || d->streaming > 1) return false;
+  if (d->forcing < 0 || d->forcing > 1) return false;
+  // population addressing uses 32-bit byte offsets within each opposite pair
+  // of populations (and within the FP32/FP64 adjoint arrays of one population):
+  // 2 N bytes-per-value < 2^32.  The product is bounded factor by factor so
+  // that it cannot overflow.
+  const long long limit = (1ll << 31) / (d->precision == PFLBM_FP64 ? 8 : 4);
+  const long long nxy = (long long)d->nx * d->ny;
+  if (nxy >= limit || nxy * d->nz >= limit) return false;
+  // one-plane kernels launch a block per (tile, plane): the grid's work-items
+  // along x must stay below 2^32 (reached only by thin, heavily padded shapes)
+  int bx, by;
+  tile_shape(d->nx, bx, by);
+  const long long tiles = (long long)((d->nx + bx - 1) / bx) * ((d->ny + by - 1) / by);
+  if (tiles * d->nz * 256 >= (1ll << 32)) return false;
+  return true;
+}
+
+struct Layout {
+  int bx, by, tiles_x, tiles_y;
+  int zc, nchunks;          // z-chunks of the marching step kernel
+  unsigned nblocks;         // one-plane kernels: tiles x nz
+  unsigned nblocks_step;    // step kernel: tiles x nchunks
+  long long N;
+  size_t off_h[2], off_g[2], off_phi[2], off_mask, off_nbr, off_part, off_red, total;
+  size_t bytes_h, bytes_g, bytes_phi;
+};
+
 Layout make_layout(const pflbm_desc* d) {
   Layout L{};
-  L.bx = d->nx > 32 ? PFLBM_TILE_X : (d->nx > 16 ? 32 : 16);
-  L.by = 256 / L.bx;
+  tile_shape(d->nx, L.bx, L.by);
   L.tiles_x = (d->nx + L.bx - 1) / L.bx;
   L.tiles_y = (d->ny + L.by - 1) / L.by;
   L.nblocks = (unsigned)L.tiles_x * (unsigned)L.tiles_y * (unsigned)d->nz;
@@ -481,9 +495,18 @@ pflbm_status do_step_states(pflbm_ctx* c, void* src, void* dst, int64_t n, int32
 template <typename S>
 pflbm_status do_profile(pflbm_ctx* c, int64_t n, double* out_ms) {
   // events around every launch, read back once at the end (no per-step sync)
-  std::vector<hipEvent_t> ev((size_t)(2 * n + 1));
-  for (auto& e : ev)
-    if (pflbm_status s = check_hip(c, hipEventCreate(&e), "pflbm_profile_step event")) return s;
+  std::vector<hipEvent_t> ev;
+  try {
+    ev.resize((size_t)(2 * n + 1), nullptr);
+  } catch (...) {
+    return fail(c, PFLBM_ERR_ARG, "pflbm_profile_step: too many steps for the host event list");
+  }
+  for (size_t k = 0; k < ev.size(); ++k) {
+    if (pflbm_status s = check_hip(c, hipEventCreate(&ev[k]), "pflbm_profile_step event")) {
+      for (size_t j = 0; j < k; ++j) (void)hipEventDestroy(ev[j]);
+      return s;
+    }
+  }
   (void)hipEventRecord(ev[0], c->stream);
   for (int64_t s = 0; s < n; ++s) {
     one_step<S>(c, ev[2 * s + 1]);
@@ -544,7 +567,9 @@ pflbm_status do_init(pflbm_ctx* c, const double* phi0, const double* u0, const d
   c->steps = 0;
   c->phi_ok = false;
   ensure_phi<S>(c);
-  return check_hip(c, hipGetLastError(), "pflbm_init_equilibrium");
+  const pflbm_status s = check_hip(c, hipGetLastError(), "pflbm_init_equilibrium");
+  c->initialised = s == PFLBM_OK;
+  return s;
 }
 
 template <typename S, int RULE>
@@ -731,7 +756,6 @@ pflbm_status pflbm_init_equilibrium(pflbm_ctx* c, const double* phi0, const doub
   if (!c) return PFLBM_ERR_ARG;
   if (!phi0) return fail(c, PFLBM_ERR_ARG, "phi0 is NULL");
   if (c->d.has_mask && !c->mask_set) return fail(c, PFLBM_ERR_STATE, "mask not set");
-  c->initialised = true;
   DISPATCH(c, do_init, c, phi0, u0, p0);
 }
 
@@ -814,7 +838,7 @@ pflbm_status pflbm_load_state(pflbm_ctx* c, const void* src, int64_t step_count)
                        c->stream);
   c->phi_ok = true;
   c->steps = step_count;
-  c->initialised = true;
+  c->initialised = e == hipSuccess;
   return check_hip(c, e, "pflbm_load_state");
 }
 

@@ -47,6 +47,11 @@ class Simulation:
 
     Fields handed in or out are float64 torch tensors on the context's device
     with shapes [nz, ny, nx] (scalars) and [3, nz, ny, nx] (vectors).
+
+    The library enqueues on the stream that was current at creation.  A call
+    made while another stream is current is ordered after the work already on
+    that stream and before what is queued on it next, and the tensors it
+    touches are marked as in use on the library's stream.
     """
 
     def __init__(self, nx: int, ny: int, nz: int, periodic=(True, False, True),
@@ -83,7 +88,7 @@ class Simulation:
         if solid is not None:
             m = torch.as_tensor(np.asarray(solid, dtype=np.uint8)).reshape(-1).to(self.device)
             self._mask = m
-            check(self.lib.pflbm_set_mask(self.ctx, _ptr(m)), self.ctx, "pflbm_set_mask")
+            self._run("pflbm_set_mask", self.lib.pflbm_set_mask, _ptr(m), keep=(m,))
 
     def __del__(self):
         try:
@@ -95,6 +100,18 @@ class Simulation:
             pass
 
     # ---- helpers -------------------------------------------------------------
+    def _run(self, name, fn, *args, keep=()):
+        cur = torch.cuda.current_stream(self.device)
+        other = cur != self.stream
+        if other:
+            self.stream.wait_stream(cur)
+        check(fn(self.ctx, *args), self.ctx, name)
+        if other:
+            cur.wait_stream(self.stream)
+            for t in keep:
+                if t is not None:
+                    t.record_stream(self.stream)
+
     def _f64(self, a, shape) -> torch.Tensor:
         t = torch.as_tensor(a, dtype=torch.float64).to(self.device).reshape(shape).contiguous()
         return t
@@ -102,23 +119,22 @@ class Simulation:
     # ---- forward -------------------------------------------------------------
     def set_params(self, p) -> None:
         s = _params_struct(p)
-        check(self.lib.pflbm_set_params(self.ctx, C.byref(s)), self.ctx, "pflbm_set_params")
+        self._run("pflbm_set_params", self.lib.pflbm_set_params, C.byref(s))
 
     def init_equilibrium(self, phi0, u0=None, pstar0=None) -> None:
         phi = self._f64(phi0, (-1,))
         u = None if u0 is None else self._f64(u0, (-1,))
         p = None if pstar0 is None else self._f64(pstar0, (-1,))
         self._init_keep = (phi, u, p)   # alive until the kernels have read them
-        check(self.lib.pflbm_init_equilibrium(self.ctx, _ptr(phi), _ptr(u), _ptr(p)), self.ctx,
-              "pflbm_init_equilibrium")
+        self._run("pflbm_init_equilibrium", self.lib.pflbm_init_equilibrium, _ptr(phi), _ptr(u),
+                  _ptr(p), keep=(phi, u, p))
 
     def set_check_interval(self, every: int) -> None:
         """Check sum(phi), sum(p*) for NaN/Inf every `every` steps (0 = off)."""
-        check(self.lib.pflbm_set_check_interval(self.ctx, int(every)), self.ctx,
-              "pflbm_set_check_interval")
+        self._run("pflbm_set_check_interval", self.lib.pflbm_set_check_interval, int(every))
 
     def step(self, n: int = 1) -> None:
-        check(self.lib.pflbm_step(self.ctx, int(n)), self.ctx, "pflbm_step")
+        self._run("pflbm_step", self.lib.pflbm_step, int(n))
 
     @property
     def step_count(self) -> int:
@@ -129,26 +145,26 @@ class Simulation:
         phi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
         p = torch.empty(self.shape, dtype=torch.float64, device=self.device)
-        check(self.lib.pflbm_read_moments(self.ctx, _ptr(phi), _ptr(u), _ptr(p)), self.ctx,
-              "pflbm_read_moments")
+        self._run("pflbm_read_moments", self.lib.pflbm_read_moments, _ptr(phi), _ptr(u), _ptr(p),
+                  keep=(phi, u, p))
         return phi, u, p
 
     def phi(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if out is None:
             out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
-        check(self.lib.pflbm_read_phi(self.ctx, _ptr(out)), self.ctx, "pflbm_read_phi")
+        self._run("pflbm_read_phi", self.lib.pflbm_read_phi, _ptr(out), keep=(out,))
         return out
 
     def populations(self):
         h = torch.empty((self.q_h, self.N), dtype=torch.float64, device=self.device)
         g = torch.empty((27, self.N), dtype=torch.float64, device=self.device)
-        check(self.lib.pflbm_read_populations(self.ctx, _ptr(h), _ptr(g)), self.ctx,
-              "pflbm_read_populations")
+        self._run("pflbm_read_populations", self.lib.pflbm_read_populations, _ptr(h), _ptr(g),
+                  keep=(h, g))
         return h, g
 
     def reduce(self) -> np.ndarray:
         out = (C.c_double * 5)()
-        check(self.lib.pflbm_reduce(self.ctx, out), self.ctx, "pflbm_reduce")
+        self._run("pflbm_reduce", self.lib.pflbm_reduce, out)
         return np.array(out[:])
 
     def state_bytes(self) -> int:
@@ -157,60 +173,58 @@ class Simulation:
     def save_state(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if out is None:
             out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
-        check(self.lib.pflbm_save_state(self.ctx, _ptr(out)), self.ctx, "pflbm_save_state")
+        self._run("pflbm_save_state", self.lib.pflbm_save_state, _ptr(out), keep=(out,))
         return out
 
     def load_state(self, buf: torch.Tensor, step_count: int) -> None:
-        check(self.lib.pflbm_load_state(self.ctx, _ptr(buf), int(step_count)), self.ctx,
-              "pflbm_load_state")
+        self._run("pflbm_load_state", self.lib.pflbm_load_state, _ptr(buf), int(step_count),
+                  keep=(buf,))
 
     def step_states(self, src: torch.Tensor, dst: torch.Tensor, n: int, flags: int = 0) -> None:
         """One step from saved state `src` (level n) into buffer `dst` (level
         n + 1); flags as in pflbm.h (write src's phi, leave dst's phi unformed)."""
-        check(self.lib.pflbm_step_states(self.ctx, _ptr(src), _ptr(dst), int(n), int(flags)),
-              self.ctx, "pflbm_step_states")
+        self._run("pflbm_step_states", self.lib.pflbm_step_states, _ptr(src), _ptr(dst), int(n),
+                  int(flags), keep=(src, dst))
 
     def profile_step(self, n: int):
         """Steps n times under HIP events; returns milliseconds
         (collide-stream kernels summed, phi-update kernels summed, total)."""
         out = (C.c_double * 3)()
-        check(self.lib.pflbm_profile_step(self.ctx, int(n), out), self.ctx, "pflbm_profile_step")
+        self._run("pflbm_profile_step", self.lib.pflbm_profile_step, int(n), out)
         return float(out[0]), float(out[1]), float(out[2])
 
     def sync(self) -> None:
-        check(self.lib.pflbm_sync(self.ctx), self.ctx, "pflbm_sync")
+        self._run("pflbm_sync", self.lib.pflbm_sync)
 
     # ---- reverse mode ----------------------------------------------------------
     def adjoint_attach(self) -> None:
         n = self.lib.pflbm_adjoint_workspace_bytes(C.byref(self.desc))
         if self._adj_ws is None:
             self._adj_ws = torch.empty(n, dtype=torch.uint8, device=self.device)
-        check(self.lib.pflbm_adjoint_attach(self.ctx, _ptr(self._adj_ws), n), self.ctx,
-              "pflbm_adjoint_attach")
+        self._run("pflbm_adjoint_attach", self.lib.pflbm_adjoint_attach, _ptr(self._adj_ws), n)
 
     def adjoint_reset(self) -> None:
-        check(self.lib.pflbm_adjoint_reset(self.ctx), self.ctx, "pflbm_adjoint_reset")
+        self._run("pflbm_adjoint_reset", self.lib.pflbm_adjoint_reset)
 
     def adjoint_inject_phi(self, dl_dphi: torch.Tensor) -> None:
         t = self._f64(dl_dphi, (-1,))
         self._inj_keep = t
-        check(self.lib.pflbm_adjoint_inject_phi(self.ctx, _ptr(t)), self.ctx,
-              "pflbm_adjoint_inject_phi")
+        self._run("pflbm_adjoint_inject_phi", self.lib.pflbm_adjoint_inject_phi, _ptr(t), keep=(t,))
 
     def adjoint_step(self, state_n: torch.Tensor, n: int) -> None:
-        check(self.lib.pflbm_adjoint_step(self.ctx, _ptr(state_n), int(n)), self.ctx,
-              "pflbm_adjoint_step")
+        self._run("pflbm_adjoint_step", self.lib.pflbm_adjoint_step, _ptr(state_n), int(n),
+                  keep=(state_n,))
 
     def adjoint_init(self, u0=None) -> torch.Tensor:
         u = None if u0 is None else self._f64(u0, (-1,))
         out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
-        check(self.lib.pflbm_adjoint_init(self.ctx, _ptr(u), _ptr(out)), self.ctx,
-              "pflbm_adjoint_init")
+        self._run("pflbm_adjoint_init", self.lib.pflbm_adjoint_init, _ptr(u), _ptr(out),
+                  keep=(u, out))
         return out
 
     def adjoint_grads(self):
         out = (C.c_double * 2)()
-        check(self.lib.pflbm_adjoint_grads(self.ctx, out), self.ctx, "pflbm_adjoint_grads")
+        self._run("pflbm_adjoint_grads", self.lib.pflbm_adjoint_grads, out)
         return float(out[0]), float(out[1])
 
 

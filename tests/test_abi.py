@@ -63,6 +63,24 @@ def test_workspace_sizes_and_invalid_descriptions():
     assert lib.pflbm_status_string(L.PFLBM_ERR_UNSTABLE).decode().startswith("unstable")
 
 
+@pytest.mark.parametrize("precision,nz_ok", [(0, 511), (1, 1023), (2, 1023)])
+def test_lattice_size_limits_are_checked_on_the_host(precision, nz_ok):
+    """The largest accepted lattice of a 1024 x 512 cross-section (2 N times the
+    value size below 2^32), one plane more is refused; products that overflow
+    64 bits and thin shapes whose launch grid reaches 2^32 work-items are
+    refused too."""
+    L, lib = _lib()
+    def ws(nx, ny, nz):
+        return lib.pflbm_workspace_bytes(C.byref(L.Desc(nx, ny, nz, 0, precision, 1, 0)))
+    assert ws(1024, 512, nz_ok) > 0
+    assert ws(1024, 512, nz_ok + 1) == 0
+    for dims in ((1 << 21,) * 3, (2 ** 31 - 1,) * 3, (1 << 30, 1 << 30, 4), (1, 1 << 30, 1 << 30)):
+        assert ws(*dims) == 0, dims
+    # 1 x 1 x nz: one 16 x 16 tile per plane, 256 work-items per cell
+    assert ws(1, 1, (1 << 24) - 1) > 0
+    assert ws(1, 1, 1 << 24) == 0
+
+
 def test_parameter_validation_without_a_gpu():
     """set_params checks arguments on the host (the workspace pointer is never
     dereferenced by create/set_params/destroy)."""
