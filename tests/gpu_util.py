@@ -1,4 +1,5 @@
 """Shared helpers of the GPU tests (host-side glue only, no method arithmetic)."""
+import math
 import sys
 
 import numpy as np
@@ -35,7 +36,9 @@ def normwise(a, ref):
     a = torch.as_tensor(a, dtype=torch.float64).cpu()
     ref = torch.as_tensor(ref, dtype=torch.float64).cpu()
     den = ref.abs().max().item()
-    return (a - ref).abs().max().item() / (den if den > 0 else 1.0)
+    v = (a - ref).abs().max().item() / (den if den > 0 else 1.0)
+    # a NaN on either side counts as the worst error (max() would skip it)
+    return v if math.isfinite(v) else math.inf
 
 
 def oracle_setup(wl, collision):
