@@ -20,6 +20,9 @@ the bubble's centre of mass weights the gas region (phi < 1/2) with 1 - phi
 overshoot of phi above 1, which over a liquid volume ~2000 times the
 bubble's outweighs the bubble; that sum is reported beside it).
 
+Also recorded: the bubble's volume (cells with phi < 1/2) against the
+initial sphere at each sample.
+
 Host-side glue only.  Run as a script:
     python tests/rising_bubble_study.py [--cases 1 2 3 4] [--D 32] [--precision fp32]
 """
@@ -104,7 +107,8 @@ def run(case: int, D: int, precision: str = "fp32", tmax: float = 10.0, every: f
     del wl.phi0, wl.pstar0, wl.u0
     m0 = sim.reduce()[0]
     t0 = time.time()
-    ts, ys, ys_all, done, finite = [], [], [], 0, True
+    ts, ys, ys_all, vol, done, finite = [], [], [], [], 0, True
+    v_sphere = math.pi / 6.0 * D ** 3
     for i in range(int(round(tmax / every)) + 1):
         s = int(round(i * every * c["t_ref"]))
         if s > done:
@@ -120,13 +124,15 @@ def run(case: int, D: int, precision: str = "fp32", tmax: float = 10.0, every: f
         ys_all.append(float((light * yy).sum() / light.sum()))
         gas = torch.where(phi < 0.5, light, torch.zeros_like(light))
         ys.append(float((gas * yy).sum() / gas.sum()))
+        # the bubble's volume (cells with phi < 1/2) against the initial sphere
+        vol.append(float((phi < 0.5).sum()) / v_sphere)
         ts.append(i * every)
         del phi, light, gas
         if log:
             log(f"  case {case} D={D} {precision}: t*={i * every:5.2f} step {s:6d} "
-                f"centre {ys[-1]:9.3f} ({time.time() - t0:.0f} s)")
+                f"centre {ys[-1]:9.3f} volume {vol[-1]:.3f} ({time.time() - t0:.0f} s)")
     out = dict(c, precision=precision, s_bulk=s_bulk, steps=done, finite=finite, tstar=ts,
-               centre=ys, centre_all_cells=ys_all, seconds=time.time() - t0,
+               centre=ys, centre_all_cells=ys_all, bubble_volume=vol, seconds=time.time() - t0,
                mass_drift=float((sim.reduce()[0] - m0) / m0) if finite else None,
                re_paper=_G[f"Re_PFLBM_case{case}"])
     tv = {round(t, 6): y for t, y in zip(ts, ys)}
