@@ -122,6 +122,12 @@ typedef struct {
                              second-order rate omega(phi) (default), else in (0, 2).
                              The viscous force F_mu then recovers the trace part of
                              the strain rate with this rate.  Ignored by BGK      */
+  double rho_g_ref;       /* body force F_b = (rho(phi) - rho_g_ref) g.  0 (default):
+                             gravity on the whole density, as written in the paper;
+                             rho_H: its buoyant part only, the heavy phase's
+                             hydrostatic pressure taken into p (the same flow in
+                             the incompressible limit, with p* of a rising light
+                             phase no longer drifting with its height); finite  */
 } pflbm_params;
 
 /* Bytes of device workspace for a context with this description (256-aligned
@@ -145,7 +151,7 @@ pflbm_status pflbm_destroy(pflbm_ctx* ctx);
 
 /* Validates and sets the physical parameters (tau > 1/2, M > 0, xi > 0,
  * sigma >= 0, rho > 0, 0 < s_high < 2, normal_eps > 0, s_bulk = 0 or in
- * (0, 2)).  Takes effect for the
+ * (0, 2), rho_g_ref finite).  Takes effect for the
  * next step. */
 pflbm_status pflbm_set_params(pflbm_ctx* ctx, const pflbm_params* params);
 

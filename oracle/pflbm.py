@@ -27,7 +27,10 @@ One step n -> n+1 (paper sec. "Conservative Allen-Cahn model"):
   S6  mu_phi = 4 beta phi (phi-1)(phi-1/2) - kappa lap phi,
       beta = 12 sigma/xi, kappa = 3 sigma xi / 2
   S7  p* = sum_i g_i (eq. zeroth_moment_hydro), j = sum_i c_i g_i
-  S8  F_s = mu_phi grad phi, F_b = rho g, F_p = -p* c_s^2 (rho_H - rho_L) grad phi
+  S8  F_s = mu_phi grad phi, F_b = (rho - rho_g_ref) g (rho_g_ref = 0 as the
+      paper writes it; rho_H applies the buoyant part only, a reading that
+      moves the heavy phase's hydrostatic pressure into p),
+      F_p = -p* c_s^2 (rho_H - rho_L) grad phi
   S9  u' = j + (F_s + F_b + F_p) / (2 rho)
   S10 Pi_neq = sum_i c_i c_i^T (g_i - g_i^eq(p*, u')),
       F_mu = -(1 - omega/2)(rho_H - rho_L) Pi_neq grad phi
@@ -91,13 +94,15 @@ class OracleParams:
     s_bulk: float = 0.0     # 0: the bulk mode of g relaxes with omega(phi)
     forcing: str = "first"  # "first" or "guo" (source of the g collision, S12)
     phase_lattice: str = "d3q15"  # or "d3q27" (the paper's own 3D phase lattice)
+    rho_g_ref: float = 0.0  # F_b = (rho - rho_g_ref) g
 
     @classmethod
     def from_workload(cls, p, collision="mrt", forcing="first",
                       phase_lattice="d3q15") -> "OracleParams":
         return cls(p.tau_H, p.tau_L, p.mobility, p.xi, p.sigma, p.rho_H, p.rho_L,
                    tuple(p.g), p.s_high, collision, p.normal_eps,
-                   float(getattr(p, "s_bulk", 0.0)), forcing, phase_lattice)
+                   float(getattr(p, "s_bulk", 0.0)), forcing, phase_lattice,
+                   float(getattr(p, "rho_g_ref", 0.0)))
 
 
 def phase_lattice(name: str) -> Lattice:
@@ -232,7 +237,7 @@ def collide(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
     # S8
     Fs = mu[None, :] * grad
     gvec = torch.tensor(prm.g, dtype=F64)[:, None]
-    Fb = rho[None, :] * gvec
+    Fb = (rho - prm.rho_g_ref)[None, :] * gvec
     Fp = -(pstar * CS2 * drho)[None, :] * grad
     # S9
     u1 = j + (Fs + Fb + Fp) / (2.0 * rho[None, :])

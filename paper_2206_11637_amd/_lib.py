@@ -28,7 +28,7 @@ class Params(C.Structure):
                 ("xi", C.c_double), ("sigma", C.c_double), ("rho_H", C.c_double),
                 ("rho_L", C.c_double), ("g", C.c_double * 3), ("s_high", C.c_double),
                 ("fp16_scale_log2", C.c_double * 2), ("normal_eps", C.c_double),
-                ("s_bulk", C.c_double)]
+                ("s_bulk", C.c_double), ("rho_g_ref", C.c_double)]
 
 
 # name: (restype, argtypes)

@@ -92,7 +92,8 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   pair_moments<R, true, Q_G>(g, jx, jy, jz, Pi);
   const R third = R(1) / R(3);
   const R cgr = mu - p * third * P.drho;
-  const R F0x = cgr * Gx + rho * P.gx, F0y = cgr * Gy + rho * P.gy, F0z = cgr * Gz + rho * P.gz;
+  const R brho = rho - P.rho_gref;
+  const R F0x = cgr * Gx + brho * P.gx, F0y = cgr * Gy + brho * P.gy, F0z = cgr * Gz + brho * P.gz;
   const R i2 = R(0.5) / rho;
   const R u1x = jx + F0x * i2, u1y = jy + F0y * i2, u1z = jz + F0z * i2;
   const R p3 = p * third;

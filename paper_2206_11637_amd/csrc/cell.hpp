@@ -34,6 +34,7 @@ struct Phys {
   R s_high;           // rate of degree >= 3 moments (MRT)
   R eps2;             // eps^2: n = grad phi / sqrt(|grad phi|^2 + eps^2)
   R s_bulk;           // rate of the bulk mode of g (MRT); 0: the second-order rate
+  R rho_gref;         // F_b = (rho - rho_gref) g
 };
 
 // second-moment tensor of a population set, symmetric storage xx yy zz xy xz yz
@@ -125,9 +126,10 @@ __device__ __forceinline__ void prologue(R phi, R dphi, const R (&g)[Q_G], R Gx,
 
   // F_s + F_p share the direction grad phi; F_b = rho g
   const R cgrad = mu - p * (R(1) / R(3)) * P.drho;
-  const R F0x = cgrad * Gx + c.rho * P.gx;
-  const R F0y = cgrad * Gy + c.rho * P.gy;
-  const R F0z = cgrad * Gz + c.rho * P.gz;
+  const R brho = c.rho - P.rho_gref;
+  const R F0x = cgrad * Gx + brho * P.gx;
+  const R F0y = cgrad * Gy + brho * P.gy;
+  const R F0z = cgrad * Gz + brho * P.gz;
   const R inv2rho = R(0.5) / c.rho;
   const R u1x = jx + F0x * inv2rho;
   const R u1y = jy + F0y * inv2rho;

@@ -208,6 +208,7 @@ Phys<R> make_phys(const pflbm_params& p, int32_t collision) {
   P.s_high = R(p.s_high);
   P.eps2 = R(p.normal_eps * p.normal_eps);
   P.s_bulk = collision == PFLBM_MRT ? R(p.s_bulk) : R(0);
+  P.rho_gref = R(p.rho_g_ref);
   return P;
 }
 
@@ -675,6 +676,7 @@ pflbm_status params_ok(const pflbm_params* p, std::string& why) {
     return PFLBM_ERR_ARG;
   for (int k = 0; k < 3; ++k)
     if (bad(!std::isfinite(p->g[k]), "g must be finite")) return PFLBM_ERR_ARG;
+  if (bad(!std::isfinite(p->rho_g_ref), "rho_g_ref must be finite")) return PFLBM_ERR_ARG;
   for (int k = 0; k < 2; ++k) {
     const double v = p->fp16_scale_log2[k];
     if (bad(!(std::fabs(v) <= 24) || v != std::floor(v), "fp16_scale_log2 must be integers in [-24, 24]"))
@@ -718,6 +720,7 @@ pflbm_status pflbm_create(const pflbm_desc* desc, void* d_workspace, size_t byte
   p.fp16_scale_log2[1] = 12;
   p.normal_eps = 1e-4;
   p.s_bulk = 0.0;
+  p.rho_g_ref = 0.0;
   c->p = p;
   *out = c;
   return PFLBM_OK;

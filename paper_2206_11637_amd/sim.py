@@ -39,6 +39,7 @@ def _params_struct(p) -> Params:
         s.fp16_scale_log2[k] = v
     s.normal_eps = get("normal_eps")
     s.s_bulk = (p.get("s_bulk", 0.0) if isinstance(p, dict) else getattr(p, "s_bulk", 0.0))
+    s.rho_g_ref = (p.get("rho_g_ref", 0.0) if isinstance(p, dict) else getattr(p, "rho_g_ref", 0.0))
     return s
 
 

@@ -74,7 +74,9 @@ def constants(case: int, D: int) -> dict:
                 tau_L=3.0 * nu_L + 0.5, mu_H=mu_H, rho_L=rho_L, t_ref=math.sqrt(D / g))
 
 
-def setup(case: int, D: int, s_bulk: float = 1.0):
+def setup(case: int, D: int, s_bulk: float = 1.0, buoyant: bool = False):
+    """buoyant: gravity acts on rho - rho_H (rho_g_ref = rho_H) and the run
+    starts at p* = 0; otherwise on rho, with the hydrostatic start."""
     c = constants(case, D)
     lx, ly, lz = (int(round(v * D)) for v in _G["domain"])        # the paper's x, y, z
     nx, ny, nz = lx, lz, ly                                        # its vertical z is our y
@@ -86,10 +88,10 @@ def setup(case: int, D: int, s_bulk: float = 1.0):
     phi0 = W.tanh_profile(r - 0.5 * D, _G["xi"])
     del r
     rho = c["rho_L"] + phi0 * (1.0 - c["rho_L"])
-    pstar = 3.0 * phi0 * c["g"] * (cz - y) / rho
+    pstar = np.zeros_like(rho) if buoyant else 3.0 * phi0 * c["g"] * (cz - y) / rho
     p = W.Params(tau_H=c["tau_H"], tau_L=c["tau_L"], mobility=_G["mobility"], xi=_G["xi"],
                  sigma=c["sigma"], rho_H=1.0, rho_L=c["rho_L"], g=(0.0, -c["g"], 0.0),
-                 s_bulk=s_bulk)
+                 s_bulk=s_bulk, rho_g_ref=1.0 if buoyant else 0.0)
     wl = W.Workload(f"rising_bubble_case{case}_D{D}_{nx}x{ny}x{nz}", nx, ny, nz,
                     (True, False, True), p, phi0, np.zeros((3, nz, ny, nx)), pstar, None,
                     int(math.ceil(10.0 * c["t_ref"])))
@@ -97,11 +99,11 @@ def setup(case: int, D: int, s_bulk: float = 1.0):
 
 
 def run(case: int, D: int, precision: str = "fp32", tmax: float = 10.0, every: float = 1.0,
-        s_bulk: float = 1.0, log=None):
+        s_bulk: float = 1.0, log=None, buoyant: bool = False):
     import torch
 
     from paper_2206_11637_amd.sim import from_workload
-    wl, c = setup(case, D, s_bulk)
+    wl, c = setup(case, D, s_bulk, buoyant)
     yy = (torch.arange(wl.ny, dtype=torch.float64, device="cuda:0") + 0.5).view(1, wl.ny, 1)
     sim = from_workload(wl, precision=precision, collision="mrt")
     del wl.phi0, wl.pstar0, wl.u0
@@ -131,7 +133,8 @@ def run(case: int, D: int, precision: str = "fp32", tmax: float = 10.0, every: f
         if log:
             log(f"  case {case} D={D} {precision}: t*={i * every:5.2f} step {s:6d} "
                 f"centre {ys[-1]:9.3f} volume {vol[-1]:.3f} ({time.time() - t0:.0f} s)")
-    out = dict(c, precision=precision, s_bulk=s_bulk, steps=done, finite=finite, tstar=ts,
+    out = dict(c, precision=precision, s_bulk=s_bulk, buoyant=buoyant, steps=done, finite=finite,
+               tstar=ts,
                centre=ys, centre_all_cells=ys_all, bubble_volume=vol, seconds=time.time() - t0,
                mass_drift=float((sim.reduce()[0] - m0) / m0) if finite else None,
                re_paper=_G[f"Re_PFLBM_case{case}"])
@@ -151,6 +154,8 @@ def main():
     ap.add_argument("--D", type=int, nargs="+", default=[32])
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--s-bulk", type=float, default=1.0)
+    ap.add_argument("--buoyant", action="store_true",
+                    help="gravity on rho - rho_H (rho_g_ref = rho_H), start at p* = 0")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
 
@@ -160,8 +165,9 @@ def main():
     res = []
     for D in args.D:
         for case in args.cases:
-            log(f"rising bubble case {case} D={D} {args.precision} s_bulk={args.s_bulk}")
-            r = run(case, D, args.precision, s_bulk=args.s_bulk, log=log)
+            log(f"rising bubble case {case} D={D} {args.precision} s_bulk={args.s_bulk}"
+                f"{' buoyant' if args.buoyant else ''}")
+            r = run(case, D, args.precision, s_bulk=args.s_bulk, log=log, buoyant=args.buoyant)
             k = {32: 0, 64: 1}.get(D)
             ref = r["re_paper"][k] if k is not None else None
             log(f"  Re(t* 5-10) = {r.get('Re')} (all-cell weights {r.get('Re_all_cells')}; "

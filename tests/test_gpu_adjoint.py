@@ -78,6 +78,15 @@ def test_fp64_adjoint_with_guos_full_source_matches_oracle_autograd(collision, s
     _adjoint_vs_oracle(wl, collision, 23, 4, forcing="guo")
 
 
+def test_fp64_adjoint_with_the_buoyant_body_force_matches_oracle_autograd():
+    """The reverse step with gravity on rho - rho_g_ref (the forward
+    recompute inside the reverse cell kernel carries the reference)."""
+    wl = _small("mrt", True)
+    wl = dataclasses.replace(wl, params=wl.params.copy(rho_g_ref=0.7, g=(1e-5, -3e-5, 0.0)))
+    say("case: adjoint fp64 mrt rho_g_ref=0.7 N=23 ckpt=4")
+    _adjoint_vs_oracle(wl, "mrt", 23, 4)
+
+
 def _adjoint_vs_oracle(wl, collision, nsteps, ckpt, forcing="first"):
     K = 3 if nsteps % 3 == 0 else 1
     rng = np.random.default_rng(5)

@@ -136,6 +136,33 @@ def test_bulk_mode_rate_in_reduced_precision(precision, tol_phi):
 
 
 @pytest.mark.parametrize("streaming", STREAMING)
+@pytest.mark.parametrize("collision,precision", [("mrt", "fp64"), ("bgk", "fp64"), ("mrt", "fp32")])
+def test_buoyant_body_force_matches_oracle(collision, precision, streaming):
+    """Gravity on rho - rho_g_ref (rho_g_ref = rho_H: buoyancy only): parity
+    with the oracle on a walled ragged grid with solids (FP64 to 1e-12, FP32
+    to 1e-5), and the reference changes the result against rho_g_ref = 0."""
+    p = W.Params(tau_H=0.6, tau_L=0.7, mobility=0.05, xi=4.0, sigma=5e-4, rho_L=0.05,
+                 g=(1e-5, -3e-5, 0.0), rho_g_ref=1.0)
+    wl = W.random_state(37, 19, 6, periodic=(False, False, True), params=p,
+                        solid_fraction=0.1, seed=53, steps=8, u_amp=0.02)
+    say(f"case: buoyant body force {collision} {precision} {streaming}")
+    grid = OP.Grid(wl.nx, wl.ny, wl.nz, wl.periodic, wl.solid)
+    prm = OP.OracleParams.from_workload(wl.params, collision)
+    assert prm.rho_g_ref == 1.0
+    h, g = OP.init_equilibrium(grid, wl.phi0, wl.u0, wl.pstar0)
+    h, g = OP.run(grid, prm, h, g, wl.steps)
+    sim = _sim(wl, precision, collision, streaming)
+    sim.step(wl.steps)
+    _compare_fields(sim, grid, prm, h, g, TOL64 if precision == "fp64" else 1e-5,
+                    f"rho_g_ref {collision} {precision} after {wl.steps}")
+    plain = _sim(dataclasses.replace(wl, params=p.copy(rho_g_ref=0.0)), precision, collision,
+                 streaming)
+    plain.step(wl.steps)
+    assert (plain.phi() - sim.phi()).abs().max().item() > 0 or \
+        (plain.moments()[1] - sim.moments()[1]).abs().max().item() > 1e-9
+
+
+@pytest.mark.parametrize("streaming", STREAMING)
 @pytest.mark.parametrize("collision,s_bulk", [("mrt", 0.0), ("bgk", 0.0), ("mrt", 1.2)])
 def test_full_guo_source_matches_oracle(collision, s_bulk, streaming):
     """Guo's full source for g (forcing="guo"): FP64 parity on a walled ragged

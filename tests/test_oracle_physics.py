@@ -115,6 +115,49 @@ def test_two_layer_channel_flow_matches_variable_viscosity_ode():
     assert np.abs(u[0].numpy() - uref).max() / uref.max() < 0.025
 
 
+def test_buoyant_gravity_leaves_a_heavy_fluid_at_rest_without_hydrostatic_pressure():
+    """With rho_g_ref = rho_H the body force is (rho - rho_H) g, zero in the
+    heavy phase: a heavy fluid at rest between walls with p* = 0 stays at rest
+    to rounding.  With the whole density (rho_g_ref = 0) the same start moves."""
+    H = 12
+    grid = P.Grid(3, H, 3, (True, False, True))
+    moved = []
+    for ref in (1.0, 0.0):
+        prm = P.OracleParams(0.7, 0.7, 0.05, 4.0, 0.0, 1.0, 0.1, (0.0, -1e-4, 0.0), rho_g_ref=ref)
+        h0, g0 = P.init_equilibrium(grid, np.ones((3, H, 3)), np.zeros((3, 3, H, 3)),
+                                    np.zeros((3, H, 3)))
+        h, g = P.run(grid, prm, h0, g0, 50)
+        moved.append(float((g - g0).abs().max()))
+    assert moved[0] < 1e-15
+    assert moved[1] > 1e-6
+
+
+def test_two_layer_flow_driven_by_the_buoyant_body_force():
+    """The equal-nu two-layer channel of the test above driven by
+    (rho - rho_g_ref) g along x with rho_g_ref their mean (no net force): the
+    layers are pushed in opposite directions and the steady profile solves
+    (mu u')' = -(rho - rho_g_ref) g."""
+    H, xi, tau, ga, rH, rL, ref = 24, 4.0, 0.8, 1e-5, 1.0, 0.1, 0.55
+    nu = (tau - 0.5) / 3
+    grid = P.Grid(1, H, 1, (True, False, True))
+    y = np.arange(H) + 0.5
+    yy = np.linspace(0, H, 20001)
+    ph = 0.5 + 0.5 * np.tanh(2 * (12 - yy) / xi)
+    rho = rL + ph * (rH - rL)
+    mu = rho * nu
+    S = cumulative_trapezoid(-(rho - ref) * ga, yy, initial=0)
+    I1 = cumulative_trapezoid(S / mu, yy, initial=0)
+    I2 = cumulative_trapezoid(1 / mu, yy, initial=0)
+    uref = np.interp(y, yy, I1 - I1[-1] / I2[-1] * I2)
+    assert uref.max() > 0 > uref.min()
+    prm = P.OracleParams(tau, tau, 0.02, xi, 0.0, rH, rL, (ga, 0, 0), rho_g_ref=ref)
+    u0 = np.zeros((3, H))
+    u0[0] = uref
+    h, g = _run(grid, prm, 0.5 + 0.5 * np.tanh(2 * (12 - y) / xi), u0, np.zeros(H), 3000)
+    _, u, _ = P.moments(grid, prm, h, g)
+    assert np.abs(u[0].numpy() - uref).max() / np.abs(uref).max() < 0.03
+
+
 @pytest.mark.parametrize("rL,tol", [(0.001, 0.04), (0.1, 0.05)])
 def test_two_layer_flow_with_interpolated_viscosity_at_high_density_ratio(rL, tol):
     """As above with the light phase ten times as viscous kinematically

@@ -78,6 +78,7 @@ class Params:
     fp16_scale_log2: tuple = (12.0, 12.0)
     normal_eps: float = 1e-4
     s_bulk: float = 0.0        # MRT rate of g's bulk mode; 0 = the second-order rate
+    rho_g_ref: float = 0.0     # body force (rho - rho_g_ref) g; rho_H: buoyancy only
 
     def copy(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
