@@ -48,7 +48,7 @@ Readings (where the setup leaves a choice):
 Host-side glue only: the time stepping runs in the library.  Run as a
 script for the study:
     python tests/taylor_study.py [--D 64 128] [--precision fp64 fp32]
-                                 [--gauge mid paper] [--s-bulk 1] [--every 0.5]
+                                 [--gauge mid paper buoyant] [--s-bulk 1] [--every 0.5]
                                  [--tmax 15] [--out FILE]
 """
 from __future__ import annotations
@@ -140,6 +140,10 @@ def setup(D: int, gauge: str = "mid", s_bulk: float = 1.0):
     elif gauge == "mid":
         p_liq = c.g * (ymid - y)
         p_gas = 0.0
+    elif gauge == "buoyant":
+        # gravity on rho - rho_H (rho_g_ref = rho_H): no hydrostatic pressure
+        p_liq = np.zeros_like(y)
+        p_gas = 0.0
     else:
         raise ValueError(gauge)
     rho = c.rho_L + phi0 * (1.0 - c.rho_L)
@@ -147,7 +151,8 @@ def setup(D: int, gauge: str = "mid", s_bulk: float = 1.0):
     pstar[solid] = 0.0
     phi0[solid] = 0.0
     p = W.Params(tau_H=c.tau_H, tau_L=c.tau_L, mobility=MOBILITY, xi=XI, sigma=c.sigma,
-                 rho_H=1.0, rho_L=c.rho_L, g=(0.0, -c.g, 0.0), s_bulk=s_bulk)
+                 rho_H=1.0, rho_L=c.rho_L, g=(0.0, -c.g, 0.0), s_bulk=s_bulk,
+                 rho_g_ref=1.0 if gauge == "buoyant" else 0.0)
     steps = int(math.ceil(15.0 * c.t_ref))
     wl = W.Workload(f"taylor_bubble_D{D}_{nx}x{ny}x{nz}", nx, ny, nz, (False, False, False), p,
                     phi0, np.zeros((3, nz, ny, nx)), pstar, solid, steps)
