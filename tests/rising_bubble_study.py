@@ -75,8 +75,10 @@ def constants(case: int, D: int) -> dict:
 
 
 def setup(case: int, D: int, s_bulk: float = 1.0, buoyant: bool = False):
-    """buoyant: gravity acts on rho - rho_H (rho_g_ref = rho_H) and the run
-    starts at p* = 0; otherwise on rho, with the hydrostatic start."""
+    """buoyant: gravity acts on rho - rho_H (rho_g_ref = rho_H); the liquid
+    then starts at p = 0 and the gas with the hydrostatic pressure of its net
+    upward force.  Otherwise gravity acts on rho, with the liquid's
+    hydrostatic start."""
     c = constants(case, D)
     lx, ly, lz = (int(round(v * D)) for v in _G["domain"])        # the paper's x, y, z
     nx, ny, nz = lx, lz, ly                                        # its vertical z is our y
@@ -88,7 +90,10 @@ def setup(case: int, D: int, s_bulk: float = 1.0, buoyant: bool = False):
     phi0 = W.tanh_profile(r - 0.5 * D, _G["xi"])
     del r
     rho = c["rho_L"] + phi0 * (1.0 - c["rho_L"])
-    pstar = np.zeros_like(rho) if buoyant else 3.0 * phi0 * c["g"] * (cz - y) / rho
+    if buoyant:
+        pstar = 3.0 * (1.0 - phi0) * (c["rho_L"] - 1.0) * c["g"] * (cz - y) / rho
+    else:
+        pstar = 3.0 * phi0 * c["g"] * (cz - y) / rho
     p = W.Params(tau_H=c["tau_H"], tau_L=c["tau_L"], mobility=_G["mobility"], xi=_G["xi"],
                  sigma=c["sigma"], rho_H=1.0, rho_L=c["rho_L"], g=(0.0, -c["g"], 0.0),
                  s_bulk=s_bulk, rho_g_ref=1.0 if buoyant else 0.0)
@@ -155,7 +160,7 @@ def main():
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--s-bulk", type=float, default=1.0)
     ap.add_argument("--buoyant", action="store_true",
-                    help="gravity on rho - rho_H (rho_g_ref = rho_H), start at p* = 0")
+                    help="gravity on rho - rho_H (rho_g_ref = rho_H)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
 

@@ -141,9 +141,10 @@ def setup(D: int, gauge: str = "mid", s_bulk: float = 1.0):
         p_liq = c.g * (ymid - y)
         p_gas = 0.0
     elif gauge == "buoyant":
-        # gravity on rho - rho_H (rho_g_ref = rho_H): no hydrostatic pressure
+        # gravity on rho - rho_H (rho_g_ref = rho_H): the liquid carries no
+        # hydrostatic pressure, the gas the one of its net upward force
         p_liq = np.zeros_like(y)
-        p_gas = 0.0
+        p_gas = (c.rho_L - 1.0) * c.g * (ymid - y)
     else:
         raise ValueError(gauge)
     rho = c.rho_L + phi0 * (1.0 - c.rho_L)
