@@ -94,7 +94,8 @@ def test_parameter_validation_without_a_gpu():
     good = _params_struct(W.Params())
     assert lib.pflbm_set_params(ctx, C.byref(good)) == 0
     for field, val in (("tau_H", 0.5), ("mobility", 0.0), ("xi", -1.0), ("sigma", -1e-4),
-                       ("rho_L", 0.0), ("s_high", 2.0), ("s_bulk", 2.0), ("s_bulk", -0.5)):
+                       ("rho_L", 0.0), ("s_high", 2.0), ("s_bulk", 2.0), ("s_bulk", -0.5),
+                       ("rho_g_ref", float("inf")), ("rho_g_ref", float("nan"))):
         p = _params_struct(W.Params())
         setattr(p, field, val)
         assert lib.pflbm_set_params(ctx, C.byref(p)) == L.PFLBM_ERR_ARG, field
@@ -102,6 +103,10 @@ def test_parameter_validation_without_a_gpu():
     for sb in (0.0, 1.0, 1.99):
         p = _params_struct(W.Params(s_bulk=sb))
         assert lib.pflbm_set_params(ctx, C.byref(p)) == 0, sb
+    for ref in (0.0, 1.0, -0.5):
+        p = _params_struct(W.Params(rho_g_ref=ref))
+        assert p.rho_g_ref == ref
+        assert lib.pflbm_set_params(ctx, C.byref(p)) == 0, ref
     p = _params_struct(W.Params())
     p.fp16_scale_log2[0] = 3.5
     assert lib.pflbm_set_params(ctx, C.byref(p)) == L.PFLBM_ERR_ARG
