@@ -6,7 +6,8 @@ kernels behind the C ABI and their Python binding) never calls into it, and
 the oracle shares no code, tables or helpers with that library.
 
 Contents
-  lattice   velocity sets, weights, Gram-Schmidt moment matrices (eq. mrt)
+  lattice   velocity sets (D3Q15, D3Q27, D2Q9), weights, Gram-Schmidt moment
+            matrices (eq. mrt)
   pflbm     one time step, S1-S17, written from the paper's equations
   adjoint   reverse-mode gradients of the oracle by torch autograd
   analytic  closed forms (capillary/gravity waves, Poiseuille, Laplace)
@@ -17,6 +18,6 @@ check beyond oracle == GPU): the explicit u' inside the viscous force, the
 synchronous time levels of the two sub-steps, the equilibrium initialisation
 details and the default high-order rate s_high = 1.
 """
-from .lattice import CS2, D3Q15, D3Q27  # noqa: F401
+from .lattice import CS2, D2Q9, D3Q15, D3Q27  # noqa: F401
 from .pflbm import (Grid, OracleParams, amplitude, collide, init_equilibrium,  # noqa: F401
                     interface_crossing, moments, reductions, run, step, stream)

@@ -7,6 +7,9 @@ Velocity sets (paper sec. "The lattice Boltzmann method", eq. LBE: c_i in
 D3Q27 here; the weights are the textbook ones, selected by |c|^2:
   D3Q15: 2/9 (rest), 1/9 (|c|^2 = 1), 1/72 (|c|^2 = 3)
   D3Q27: 8/27, 2/27 (|c|^2 = 1), 1/54 (|c|^2 = 2), 1/216 (|c|^2 = 3)
+  D2Q9:  4/9, 1/9 (|c|^2 = 1), 1/36 (|c|^2 = 2), in the x-y plane (c_z = 0);
+         the velocity set of the paper's two-dimensional runs (sec. "Numerical
+         experiments", standing waves), used for both lattices there
 
 MRT (paper eq. mrt, and the remark in sec. "Numerical experiments" that a
 weighted orthogonal MRT was used): the moment matrix M has one row per
@@ -96,5 +99,14 @@ def d3q27() -> Lattice:
     return Lattice("D3Q27", c, w, mon)
 
 
+def d2q9() -> Lattice:
+    c = np.array([v for v in _velocities({0, 1, 2}) if v[2] == 0], dtype=np.int64)
+    n2 = (c * c).sum(1)
+    w = np.select([n2 == 0, n2 == 1, n2 == 2], [4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0])
+    mon = sorted(((a, b, 0) for a in (0, 1, 2) for b in (0, 1, 2)), key=lambda m: (sum(m), m))
+    return Lattice("D2Q9", c, w, mon)
+
+
 D3Q15 = d3q15()
 D3Q27 = d3q27()
+D2Q9 = d2q9()

@@ -6,7 +6,9 @@ in the order below, with two-buffer (A -> B) streaming and dense
 M^-1 S M collision matrices.  Nothing here is shared with the HIP library.
 
 State: h [15, N] (phase field, D3Q15; [27, N] with the D3Q27 phase lattice the
-paper uses in 3D, phase_lattice="d3q27") and g [27, N] (hydrodynamics, D3Q27),
+paper uses in 3D, phase_lattice="d3q27") and g [27, N] (hydrodynamics, D3Q27);
+with phase_lattice="d2q9" both are D2Q9 [9, N] on an nz = 1 grid (the pair of
+the paper's two-dimensional runs, stencils over D2Q9 as well),
 post-streaming, with N = nx*ny*nz cells and cell index x + nx*(y + ny*z).
 Solid cells hold zeros and are never updated.
 
@@ -72,7 +74,7 @@ from typing import Optional, Union
 import numpy as np
 import torch
 
-from .lattice import CS2, D3Q15, D3Q27, Lattice
+from .lattice import CS2, D2Q9, D3Q15, D3Q27, Lattice
 
 Num = Union[float, torch.Tensor]
 F64 = torch.float64
@@ -83,7 +85,7 @@ class OracleParams:
     tau_H: float
     tau_L: float
     mobility: Num
-    xi: float
+    xi: Num
     sigma: Num
     rho_H: float
     rho_L: float
@@ -93,7 +95,8 @@ class OracleParams:
     eps_normal: float = 1e-4
     s_bulk: float = 0.0     # 0: the bulk mode of g relaxes with omega(phi)
     forcing: str = "first"  # "first" or "guo" (source of the g collision, S12)
-    phase_lattice: str = "d3q15"  # or "d3q27" (the paper's own 3D phase lattice)
+    phase_lattice: str = "d3q15"  # or "d3q27" (the paper's own 3D phase lattice), or
+                                  # "d2q9": the D2Q9 pair of the paper's 2D runs (nz = 1)
     rho_g_ref: float = 0.0  # F_b = (rho - rho_g_ref) g
 
     @classmethod
@@ -106,12 +109,21 @@ class OracleParams:
 
 
 def phase_lattice(name: str) -> Lattice:
-    """Velocity set of the phase field: D3Q15 (default) or D3Q27."""
+    """Velocity set of the phase field: D3Q15 (default), D3Q27, or D2Q9 (the
+    two-dimensional pair)."""
     if name == "d3q15":
         return D3Q15
     if name == "d3q27":
         return D3Q27
+    if name == "d2q9":
+        return D2Q9
     raise ValueError(name)
+
+
+def hydro_lattice(name: str) -> Lattice:
+    """Velocity set of the hydrodynamics (and of the grad/lap stencils): D3Q27
+    with either 3D phase lattice, D2Q9 in the two-dimensional pair."""
+    return D2Q9 if name == "d2q9" else D3Q27
 
 
 class Grid:
@@ -198,7 +210,9 @@ def _rates(lat: Lattice, low: torch.Tensor, s_high, bgk: bool, n: int) -> torch.
 
 def collide(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
     """S1-S15.  Returns (h*, g*, aux) where aux holds the cell moments and forces."""
-    LH, LG = phase_lattice(prm.phase_lattice), D3Q27
+    LH, LG = phase_lattice(prm.phase_lattice), hydro_lattice(prm.phase_lattice)
+    if LG is D2Q9 and (grid.nz != 1 or prm.s_bulk > 0):
+        raise ValueError("the D2Q9 pair needs nz = 1 and no separate bulk rate")
     N = grid.N
     bgk = prm.collision == "bgk"
     drho = prm.rho_H - prm.rho_L
@@ -215,21 +229,23 @@ def collide(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
         lap = lap + 6.0 * LG.w[k] * (phik - phi)
     # S4
     normal = grad / torch.sqrt((grad * grad).sum(0) + prm.eps_normal ** 2)
-    if math.isinf(prm.xi):
+    xi_inf = math.isinf(float(prm.xi.detach()) if isinstance(prm.xi, torch.Tensor) else float(prm.xi))
+    if xi_inf:
         theta = torch.zeros(N, dtype=F64)
     else:
-        theta = 4.0 * phi * (1.0 - phi) / prm.xi
+        theta = 4.0 * phi * (1.0 - phi) / _as_t(prm.xi)
     # S5
     rho = prm.rho_L + phi * drho
     tau = prm.tau_L + phi * (prm.tau_H - prm.tau_L)
     omega = 1.0 / tau
     # S6
     sigma = _as_t(prm.sigma)
-    if math.isinf(prm.xi):
+    if xi_inf:
         mu = torch.zeros(N, dtype=F64)
     else:
-        beta = 12.0 * sigma / prm.xi
-        kappa = 1.5 * sigma * prm.xi
+        xi = _as_t(prm.xi)
+        beta = 12.0 * sigma / xi
+        kappa = 1.5 * sigma * xi
         mu = 4.0 * beta * phi * (phi - 1.0) * (phi - 0.5) - kappa * lap
     # S7
     pstar = g.sum(0)
@@ -295,7 +311,8 @@ def stream(grid: Grid, lat: Lattice, fstar: torch.Tensor) -> torch.Tensor:
 
 def step(grid: Grid, prm: OracleParams, h: torch.Tensor, g: torch.Tensor):
     hs, gs, _ = collide(grid, prm, h, g)
-    return stream(grid, phase_lattice(prm.phase_lattice), hs), stream(grid, D3Q27, gs)
+    return (stream(grid, phase_lattice(prm.phase_lattice), hs),
+            stream(grid, hydro_lattice(prm.phase_lattice), gs))
 
 
 def run(grid: Grid, prm: OracleParams, h, g, nsteps: int):
@@ -308,13 +325,14 @@ def init_equilibrium(grid: Grid, phi0, u0, pstar0, phase: str = "d3q15"):
     """h = phi0 w_i [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u], g = g^eq(p*0, u0); zero in solids.
 
     phi0 [N] or [nz,ny,nx]; u0 [3, ...]; pstar0 like phi0 (numpy or torch);
-    phase: the phase field's velocity set ("d3q15" or "d3q27").
+    phase: the phase field's velocity set ("d3q15", "d3q27" or "d2q9", the
+    last with the D2Q9 hydrodynamics).
     """
     phi0 = torch.as_tensor(phi0, dtype=F64).reshape(-1)
     u0 = torch.as_tensor(u0, dtype=F64).reshape(3, -1)
     pstar0 = torch.as_tensor(pstar0, dtype=F64).reshape(-1)
     h = equilibrium(phase_lattice(phase), phi0, u0, True)
-    g = equilibrium(D3Q27, pstar0, u0, False)
+    g = equilibrium(hydro_lattice(phase), pstar0, u0, False)
     fl = grid.fluid[None, :]
     return torch.where(fl, h, torch.zeros_like(h)), torch.where(fl, g, torch.zeros_like(g))
 
@@ -328,12 +346,12 @@ def moments(grid: Grid, prm: OracleParams, h, g):
             torch.where(fl, aux["pstar"], z))
 
 
-def reductions(grid: Grid, h, g):
+def reductions(grid: Grid, h, g, phase: str = "d3q15"):
     """[sum phi, sum p*, sum j_x, sum j_y, sum j_z] over fluid cells (fp64)."""
     fl = grid.fluid
     phi = h.sum(0)[fl].sum()
     ps = g.sum(0)[fl].sum()
-    j = (D3Q27.c.t() @ g)[:, fl].sum(1)
+    j = (hydro_lattice(phase).c.t() @ g)[:, fl].sum(1)
     return torch.stack([phi, ps, j[0], j[1], j[2]])
 
 

@@ -1,4 +1,6 @@
-"""Pin of the oracle's reverse mode against central finite differences (FP64)."""
+"""Pin of the oracle's reverse mode against central finite differences (FP64):
+dL/dM, dL/dsigma, dL/dxi (the interface width, through the counter-term and
+the chemical potential) and dL/dphi0 along random directions."""
 import dataclasses
 
 import numpy as np
@@ -26,8 +28,10 @@ def test_autograd_gradients_match_central_differences(collision):
     rng = np.random.default_rng(2)
     target = rng.normal(0, 0.05, n // K)
     args = (wl.u0, wl.pstar0, n, K, 6.0, target)
-    L, dphi, dM, ds, _ = AD.loss_and_gradients(grid, prm, wl.phi0, *args)
-    for name, val, grad in (("mobility", prm.mobility, dM), ("sigma", prm.sigma, ds)):
+    r = AD.gradients(grid, prm, wl.phi0, *args)
+    dphi, dM, ds, dxi = r["dphi0"], r["dM"], r["dsigma"], r["dxi"]
+    for name, val, grad in (("mobility", prm.mobility, dM), ("sigma", prm.sigma, ds),
+                            ("xi", prm.xi, dxi)):
         hstep = 1e-4 * val
         lp = AD.loss_only(grid, dataclasses.replace(prm, **{name: val + hstep}), wl.phi0, *args)
         lm = AD.loss_only(grid, dataclasses.replace(prm, **{name: val - hstep}), wl.phi0, *args)
