@@ -4,18 +4,27 @@ A "step" is one time step of the whole hot path over the lattice: the fused
 collide-and-stream kernel of both populations (D3Q15 phase field + D3Q27
 hydrodynamics, forces, stencils, bounce-back) followed by the phase-field
 update.  The headline workload is the rising-bubble lattice 128 x 512 x 128
-(8.4 M cells, six bounce-back faces) in FP32; the line also carries the FP64
-and FP16-storage forms and the reverse-mode cost.
+(8.4 M cells, six bounce-back faces) in FP64, the arithmetic of the paper's
+runs; the line also carries the FP32 and FP16-storage forms (each with its
+own roofline block), a hand-written streaming-copy ceiling, the reverse-mode
+cost and the gradient error of the reduced-precision forms against FP64.
 
-  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-forms]
+  python bench.py [--steps K] [--warmup W] [--runs R] [--no-cpu-baseline]
+                  [--no-forms] [--only NAME,NAME] [--precision P]
 
-Prints one JSON line.  Inputs are resident in HBM before the timed region.
+Timing: W untimed warm-up steps, then R runs of K steps each (HIP events on
+the library's stream, synchronised on both sides); the reported figures are
+those of the median run.  Kernel durations come from a second set of R runs
+with an event between consecutive launches.  Prints one JSON line.  Inputs
+are resident in HBM before the timed region.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
+import statistics
 import sys
 import time
 
@@ -34,19 +43,38 @@ CELL_KERNEL_BYTES = STEP_BYTES
 AA_CELL_KERNEL_BYTES = {"fp64": 680, "fp32": 340, "fp16s": 172}
 # the D3Q27-phase build: 27 + 27 populations
 STEP_BYTES_D3Q27 = {"fp64": 880, "fp32": 440, "fp16s": 224}
-# HBM bytes per launch of k_step on the rising-bubble lattice from rocprofv3
-# FETCH_SIZE / WRITE_SIZE, scaled by the factors a plain 2 GiB device copy
-# gives on the same box (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE); taken for
-# the current kernel (profiles/k_step_rising_bubble_128x512x128_hbm_traffic.txt)
-# and to be re-measured whenever it changes
-TRAFFIC = {"fp32": 3.405e9, "fp16s": 1.558e9, "fp64": 6.038e9}
+# HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE, scaled by the factors a plain 2 GiB device copy gives on the
+# same box (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE), keyed by form; taken for
+# the current kernel (profiles/k_step_hbm_traffic.txt) and re-measured
+# whenever it changes.  Forms without an entry report null.
+TRAFFIC = {}
+TRAFFIC_UNIT = "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
+DTYPE = {"fp32": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64"}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_form(wl, precision, steps, warmup, collision="mrt", streaming="ab", phase="d3q15"):
+def roofline(name, bytes_per_cell, cells, kernel_ms, kernel):
+    """Roofline block of one kernel: algorithmic bytes per launch over its
+    average launch duration against the 8 TB/s datasheet peak, with the
+    counter-measured traffic where the committed counters cover this form."""
+    alg = bytes_per_cell * cells
+    achieved = alg / (kernel_ms * 1e-3) / 1e9
+    tr = TRAFFIC.get(name)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": tr, "traffic_unit": TRAFFIC_UNIT,
+            "traffic_over_algorithmic": None if tr is None else round(tr / alg, 4),
+            "algorithmic_bytes_per_launch": alg, "bytes_per_cell": bytes_per_cell,
+            "kernel": kernel, "kernel_ms": round(kernel_ms, 5)}
+
+
+def time_form(name, wl, precision, steps, warmup, runs, collision="mrt", streaming="ab",
+              phase="d3q15"):
+    """Median of `runs` timed runs of `steps` steps (plain stepping), and the
+    kernels' average durations from as many profiled runs."""
     import torch
 
     from paper_2206_11637_amd.sim import from_workload
@@ -54,38 +82,98 @@ def time_form(wl, precision, steps, warmup, collision="mrt", streaming="ab", pha
                         phase_lattice=phase)
     sim.step(warmup)
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    cell_ms, phi_ms, total_ms = sim.profile_step(steps)
-    t1.record()
-    torch.cuda.synchronize()
-    wall_ms = t0.elapsed_time(t1)
+    walls, cells_ms, phis_ms = [], [], []
+    for _ in range(runs):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(sim.stream)
+        sim.step(steps)
+        t1.record(sim.stream)
+        torch.cuda.synchronize()
+        walls.append(t0.elapsed_time(t1))
+    for _ in range(runs):
+        cell_ms, phi_ms, _ = sim.profile_step(steps)
+        cells_ms.append(cell_ms / steps)
+        phis_ms.append(phi_ms / steps)
     r = sim.reduce()
+    wall = statistics.median(walls)
+    cell_avg = statistics.median(cells_ms)
+    phi_avg = statistics.median(phis_ms)
     cells = wl.cells
-    mlups = cells * steps / (wall_ms * 1e-3) / 1e6
-    cell_avg = cell_ms / steps
+    mlups = cells * steps / (wall * 1e-3) / 1e6
     if phase == "d3q27":
         kb = sb = STEP_BYTES_D3Q27[precision]
+        kernel = "k_step (D3Q27 phase lattice build)"
+    elif streaming == "aa":
+        kb, sb = AA_CELL_KERNEL_BYTES[precision], STEP_BYTES[precision]
+        kernel = "k_cell_aa (in-place collide and stream; + k_light phi gather)"
     else:
-        kb = (AA_CELL_KERNEL_BYTES if streaming == "aa" else CELL_KERNEL_BYTES)[precision]
-        sb = STEP_BYTES[precision]
-    achieved = kb * cells / (cell_avg * 1e-3) / 1e9
-    out = dict(mlups=mlups, ms_per_step=wall_ms / steps, cell_kernel_ms=cell_avg,
-               phi_kernel_ms=phi_ms / steps, cell_kernel_GBps=achieved,
-               cell_kernel_frac=achieved / HBM_PEAK_GBPS,
-               effective_GBps=mlups * sb / 1e3,
-               effective_frac=mlups * sb / 1e3 / HBM_PEAK_GBPS,
-               mass=r[0])
+        kb = sb = STEP_BYTES[precision]
+        kernel = "k_step (fused pull, phase field, collide, store)"
+    out = dict(mlups=round(mlups, 1), ms_per_step=round(wall / steps, 5),
+               runs=runs, steps_per_run=steps,
+               ms_per_step_range=[round(min(walls) / steps, 5), round(max(walls) / steps, 5)],
+               phi_kernel_ms=round(phi_avg, 5),
+               effective_frac=round(mlups * sb / 1e3 / HBM_PEAK_GBPS, 4),
+               roofline=roofline(name, kb, cells, cell_avg, kernel),
+               mass=float(r[0]))
     del sim
     torch.cuda.empty_cache()
     return out
 
 
-def adjoint_form(wl, precision, nsteps, sample_every, x0, depth, ckpt=None):
+def copy_ceiling(steps, runs):
+    """Hand-written streaming kernels with no arithmetic (pflbm_hbm_copy):
+    2 GiB plain copies with 4- and 16-byte accesses, and the FP32 step's own
+    access pattern (43 rows of N floats read and written, N = the rising-bubble
+    lattice).  GB/s counts bytes read plus bytes written."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2206_11637_amd import _lib
+    lib = _lib.load()
+    stream = torch.cuda.current_stream()
+    out = {}
+    cases = [("w4_2GiB", "w4", 1 << 31), ("w16_2GiB", "w16", 1 << 31),
+             ("w16_cached_2GiB", "w16_cached", 1 << 31),
+             ("soa43_fp32_step_pattern_128x512x128", "soa43", 43 * 4 * 128 * 512 * 128)]
+    for name, form, nbytes in cases:
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+
+        def launch():
+            _lib.check(lib.pflbm_hbm_copy(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                          nbytes, _lib.COPY_FORMS[form],
+                                          C.c_void_p(stream.cuda_stream)), None, "pflbm_hbm_copy")
+        for _ in range(3):
+            launch()
+        ts = []
+        for _ in range(runs):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(steps):
+                launch()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / steps)
+        ms = statistics.median(ts)
+        gbps = 2 * nbytes / (ms * 1e-3) / 1e9
+        assert torch.equal(a[:1024], b[:1024]) and torch.equal(a[-1024:], b[-1024:])
+        out[name] = {"ms": round(ms, 5), "GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "bytes_moved": 2 * nbytes}
+        del a, b
+        torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_run(wl, precision, nsteps, sample_every, x0, depth, ckpt=None, timed=True):
     """Forward (with checkpoints) and backward (with segment recompute) of the
-    differentiable amplitude rollout; wall times of the second of two identical
-    runs, their ratio and peak HBM."""
+    differentiable amplitude rollout, loss = sum of squared samples; wall
+    times of the second of two identical runs (timed) and the gradients."""
     import time as _t
 
     import torch
@@ -99,17 +187,18 @@ def adjoint_form(wl, precision, nsteps, sample_every, x0, depth, ckpt=None):
     phi0 = torch.tensor(wl.phi0, dtype=torch.float64, device=dev, requires_grad=True)
     M = torch.tensor(wl.params.mobility, dtype=torch.float64, requires_grad=True)
     sg = torch.tensor(wl.params.sigma, dtype=torch.float64, requires_grad=True)
+    xi = torch.tensor(wl.params.xi, dtype=torch.float64, requires_grad=True)
     u0 = torch.as_tensor(wl.u0, dtype=torch.float64).to(dev)
     p0 = torch.as_tensor(wl.pstar0, dtype=torch.float64).to(dev)
     stats = {}
-    # two identical runs, the second timed: the first warms the code objects
-    # and the allocator's pools for the checkpoint and adjoint buffers
-    for _ in range(2):
-        for t in (phi0, M, sg):
+    # two identical runs when timed, the second timed: the first warms the code
+    # objects and the allocator's pools for the checkpoint and adjoint buffers
+    for _ in range(2 if timed else 1):
+        for t in (phi0, M, sg, xi):
             t.grad = None
         torch.cuda.synchronize()
         t0 = _t.perf_counter()
-        trace = amplitude_rollout(sim, phi0, M, sg, params=wl.params, nsteps=nsteps,
+        trace = amplitude_rollout(sim, phi0, M, sg, xi=xi, params=wl.params, nsteps=nsteps,
                                   sample_every=sample_every, depth=depth, x0=x0, u0=u0, pstar0=p0,
                                   checkpoint_every=ckpt, stats=stats)
         loss = (trace ** 2).sum()
@@ -125,10 +214,35 @@ def adjoint_form(wl, precision, nsteps, sample_every, x0, depth, ckpt=None):
                forward_mlups=cells * nsteps / fwd / 1e6,
                backward_mlups=cells * nsteps / bwd / 1e6,
                checkpoints=stats.get("checkpoints"), checkpoint_every=stats.get("checkpoint_every"),
-               peak_hbm_GB=torch.cuda.max_memory_allocated() / 1e9,
-               dL_dM=float(M.grad), dL_dsigma=float(sg.grad))
+               peak_hbm_GB=torch.cuda.max_memory_allocated() / 1e9)
+    grads = dict(dM=float(M.grad), dsigma=float(sg.grad), dxi=float(xi.grad),
+                 dphi0=phi0.grad.detach().clone())
     del sim, phi0
     torch.cuda.empty_cache()
+    return out, grads
+
+
+def grad_errors(g, ref):
+    """Relative errors of a reduced-precision form's gradients against FP64
+    (parameters: |d - d_64| / |d_64|; the field dL/dphi0: max norm over max norm)."""
+    e = {k: abs(g[k] - ref[k]) / abs(ref[k]) for k in ("dM", "dsigma", "dxi")}
+    d = (g["dphi0"] - ref["dphi0"]).abs().max() / ref["dphi0"].abs().max()
+    e["dphi0_normwise"] = float(d)
+    return e
+
+
+def adjoint_form(wl, precision, nsteps, sample_every, x0, depth, ref_wl=None, ckpt=None):
+    """Reverse-mode cost of a form, plus its gradients' relative error against
+    the FP64 form of the same rollout (on ref_wl when the full lattice's FP64
+    checkpoints would not fit in HBM)."""
+    out, grads = adjoint_run(wl, precision, nsteps, sample_every, x0, depth, ckpt)
+    out.update({k: v for k, v in grads.items() if k != "dphi0"})
+    rw = ref_wl or wl
+    if ref_wl is not None:
+        _, grads = adjoint_run(rw, precision, nsteps, sample_every, x0, depth, ckpt, timed=False)
+    _, ref = adjoint_run(rw, "fp64", nsteps, sample_every, x0, depth, ckpt, timed=False)
+    out["grad_rel_err_vs_fp64"] = grad_errors(grads, ref)
+    out["grad_rel_err_lattice"] = rw.name
     return out
 
 
@@ -208,48 +322,68 @@ def long_run(wl, steps=20000, every=5000):
     return out
 
 
-def cpu_baseline():
-    """The FP64 oracle on a bounded sample of the same workload (a z-slab of
-    the rising-bubble lattice with its walls), timed on the host cores."""
-    import numpy as np
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def _oracle_steps(wl, z0, z1, threads, min_s, min_steps):
     import torch
 
-    import workloads as W
     from oracle import pflbm as OP
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
-    threads = min(threads, 16)
     torch.set_num_threads(threads)
-    wl = W.config1()
-    z0, z1 = 56, 72
     grid = OP.Grid(wl.nx, wl.ny, z1 - z0, (False, False, False))
     prm = OP.OracleParams.from_workload(wl.params, "mrt")
     h, g = OP.init_equilibrium(grid, wl.phi0[z0:z1], wl.u0[:, z0:z1], wl.pstar0[z0:z1])
     h, g = OP.step(grid, prm, h, g)   # first step builds the neighbour tables
-    # timed steps until about 15 s of host time (at least 4)
     nsteps = 0
     t = time.perf_counter()
     while True:
         h, g = OP.step(grid, prm, h, g)
         nsteps += 1
         dt = time.perf_counter() - t
-        if nsteps >= 4 and dt >= 15.0:
+        if nsteps >= min_steps and dt >= min_s:
             break
-    cells = grid.N
-    return {"value": cells * nsteps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"rising-bubble lattice cut to z in [{z0},{z1}) ({wl.nx}x{wl.ny}x{z1 - z0} "
-                      f"cells, walls on all faces), FP64 MRT, {nsteps} timed steps, {dt:.1f} s"}
+    return grid.N * nsteps / dt / 1e6, nsteps, dt, torch.get_num_threads()
+
+
+def cpu_baseline():
+    """The FP64 oracle as it stands, timed on the host: the whole rising-bubble
+    lattice at reduced steps on every thread the process is given (the
+    benchmark workload itself), and a z-slab of it on one thread."""
+    import torch
+
+    import workloads as W
+    wl = W.config1()
+    threads = torch.get_num_threads()   # follows OMP_NUM_THREADS (the host share of one GPU)
+    v, n, dt, used = _oracle_steps(wl, 0, wl.nz, threads, 5.0, 2)
+    v1, n1, dt1, _ = _oracle_steps(wl, 60, 68, 1, 8.0, 1)
+    torch.set_num_threads(threads)
+    return {"value": v, "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": f"the whole rising-bubble lattice {wl.nx}x{wl.ny}x{wl.nz} (six walls), FP64 MRT, "
+                      f"{n} timed steps after one untimed, {dt:.1f} s on {used} threads",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread": {"value": v1, "unit": "MLUPS", "cores": 1,
+                              "sample": f"z-slab {wl.nx}x{wl.ny}x8 of the same lattice (walls on all "
+                                        f"faces), {n1} timed steps, {dt1:.1f} s"}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--runs", type=int, default=5, help="timed runs; the median run is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16s", "fp64"],
-                    help="storage/arithmetic form of the headline run (default fp32)")
+    ap.add_argument("--only", default="", help="comma-separated form names (no slow legs)")
+    ap.add_argument("--precision", default="fp64", choices=["fp32", "fp16s", "fp64"],
+                    help="storage/arithmetic form of the headline run (default fp64, the paper's)")
     ap.add_argument("--adj-steps", type=int, default=4000,
                     help="steps of the Taylor-tube reverse-mode leg (sqrt(N) checkpoints)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -274,94 +408,85 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
         return
+    only = [s for s in args.only.split(",") if s]
     prec = args.precision
-    log(f"bench: rising bubble 128x512x128 {prec} mrt")
+    K, Wm, R = args.steps, args.warmup, args.runs
     wl1 = W.config1()
-    main_form = time_form(wl1, prec, args.steps, args.warmup)
-    log(f"  {prec}: {main_form['mlups']:.0f} MLUPS")
+    head_name = f"{prec}_rising_bubble_128x512x128"
+    main_form = None
+    if not only or head_name in only:
+        log(f"bench: {head_name}")
+        main_form = time_form(head_name, wl1, prec, K, Wm, R)
+        log(f"  {main_form['mlups']:.0f} MLUPS")
     forms = {}
 
-    def form(name, fn, *a):
+    def form(name, fn, *a, **kw):
+        if only and name not in only:
+            return
         log(f"bench: {name}")
+        t = time.perf_counter()
         try:
-            forms[name] = fn(*a)
+            forms[name] = fn(*a, **kw)
         except Exception as e:          # report, keep the headline line
             forms[name] = {"error": f"{type(e).__name__}: {e}"}
             torch.cuda.empty_cache()
+        log(f"  done in {time.perf_counter() - t:.1f} s")
 
+    slow = not only
     if not args.no_forms:
-        half = max(args.steps // 2, 10)
-        form("fp64_rising_bubble_128x512x128", time_form, wl1, "fp64", half, args.warmup)
-        form("rising_bubble_20k_steps_fp32_vs_fp64", long_run, wl1)
+        form("hbm_copy_ceiling", copy_ceiling, max(K // 5, 10), R)
+        for p in ("fp64", "fp32", "fp16s"):
+            if p != prec:
+                n = f"{p}_rising_bubble_128x512x128"
+                form(n, time_form, n, wl1, p, K, Wm, R)
+        if slow:
+            form("rising_bubble_20k_steps_fp32_vs_fp64", long_run, wl1)
         # the in-place AA scheme: half the population memory, a separate phi pass
-        form("fp32_in_place_aa_rising_bubble_128x512x128", time_form, wl1, "fp32", half, args.warmup,
-             "mrt", "aa")
+        n = "fp32_in_place_aa_rising_bubble_128x512x128"
+        form(n, time_form, n, wl1, "fp32", K, Wm, R, "mrt", "aa")
         # the D3Q27 phase lattice (the paper's 3D choice; a separate build)
-        form("fp32_d3q27_phase_rising_bubble_128x512x128", time_form, wl1, "fp32", half,
-             args.warmup, "mrt", "ab", "d3q27")
+        n = "fp32_d3q27_phase_rising_bubble_128x512x128"
+        form(n, time_form, n, wl1, "fp32", K, Wm, R, "mrt", "ab", "d3q27")
         del wl1
+        half = max(K // 4, 10)
         wl2 = W.config2()
-        form("fp32_drop_impact_384^3", time_form, wl2, "fp32", half, args.warmup)
-        form("fp16s_drop_impact_384^3", time_form, wl2, "fp16s", half, args.warmup)
-        form("precision_errors_drop_impact_384^3", precision_errors, wl2)
+        for p in ("fp32", "fp16s"):
+            n = f"{p}_drop_impact_384^3"
+            form(n, time_form, n, wl2, p, half, Wm, R)
+        if slow:
+            form("precision_errors_drop_impact_384^3", precision_errors, wl2)
         # one GPU's share of the 384^3 drop on 8 GPUs (z-slabs of 48 planes
         # through the drop; z wraps where the slab exchange would be)
         z0 = 192 - 24
         shard = W.Workload("drop_impact_shard_384x384x48", 384, 384, 48, (True, False, True),
                            wl2.params, wl2.phi0[z0:z0 + 48].copy(), wl2.u0[:, z0:z0 + 48].copy(),
                            wl2.pstar0[z0:z0 + 48].copy(), None, wl2.steps)
-        form("fp32_shard_384x384x48_of_drop_impact", time_form, shard, "fp32", half, args.warmup)
+        n = "fp32_shard_384x384x48_of_drop_impact"
+        form(n, time_form, n, shard, "fp32", K, Wm, R)
         del shard
         del wl2
-        # the benchmark's M = 0.01 impact goes unstable after ~1.1k steps in
-        # every precision; the 5000-step growth of the errors runs at M = 0.03
-        wl2s = W.config2(mobility=0.03)
-        form("precision_errors_drop_impact_384^3_M0.03", precision_errors, wl2s,
-             (100, 500, 1000, 5000))
-        del wl2s
-        wl3 = W.config3()
-        form("adjoint_capillary_64x128x64_fp32", adjoint_form, wl3, "fp32", wl3.steps, 10, 0, 64.0)
-        del wl3
-        wl4 = W.config4()
-        form("adjoint_taylor_bubble_128x1024x128_fp16s", adjoint_form, wl4, "fp16s",
-             args.adj_steps, 10, 64, 0.0)
-        del wl4
+        if slow:
+            # the benchmark's M = 0.01 impact goes unstable after ~1.1k steps in
+            # every precision; the 5000-step growth of the errors runs at M = 0.03
+            wl2s = W.config2(mobility=0.03)
+            form("precision_errors_drop_impact_384^3_M0.03", precision_errors, wl2s,
+                 (100, 500, 1000, 5000))
+            del wl2s
+            wl3 = W.config3()
+            form("adjoint_capillary_64x128x64_fp32", adjoint_form, wl3, "fp32", wl3.steps, 10, 0,
+                 64.0)
+            del wl3
+            wl4 = W.config4()
+            # the FP64 reference of the gradients runs on the tube at half the
+            # resolution (64x512x64), where its checkpoints fit in HBM
+            form("adjoint_taylor_bubble_128x1024x128_fp16s", adjoint_form, wl4, "fp16s",
+                 args.adj_steps, 10, 32, 0.0, W.config4(scale=2))
+            del wl4
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not only:
         log("bench: cpu baseline (oracle)")
         cpu = cpu_baseline()
-    line = {
-        "metric": METRIC,
-        "value": round(main_form["mlups"], 1),
-        "unit": "MLUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(main_form["ms_per_step"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64"}[prec],
-        "data": "synthetic",
-        "config": {"workload": "rising_bubble_128x512x128", "cells": 128 * 512 * 128,
-                   "lattices": "D3Q15+D3Q27", "collision": "mrt", "storage": prec,
-                   "streaming": "two buffers, pull, phase field fused into the step",
-                   "boundaries": "bounce-back on all faces"},
-        "roofline": {"bound": "hbm", "achieved": round(main_form["cell_kernel_GBps"], 1),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(main_form["cell_kernel_frac"], 4), "traffic": TRAFFIC.get(prec),
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
-                     "algorithmic_bytes_per_launch": CELL_KERNEL_BYTES[prec] * 128 * 512 * 128,
-                     "kernel": "k_step (fused pull, phase field, collide, store)",
-                     "bytes_per_cell": CELL_KERNEL_BYTES[prec]},
-        "step_effective": {"bytes_per_cell": STEP_BYTES[prec],
-                           "GBps": round(main_form["effective_GBps"], 1),
-                           "frac": round(main_form["effective_frac"], 4),
-                           "phi_kernel_ms": round(main_form["phi_kernel_ms"], 4),
-                           "cell_kernel_ms": round(main_form["cell_kernel_ms"], 4)},
-        "cpu_baseline": cpu,
-        "forms": forms,
-    }
+
     def _round(v):
         if isinstance(v, float):
             return float(f"{v:.5g}")
@@ -369,7 +494,33 @@ def main():
             return {k: _round(x) for k, x in v.items()}
         return v
 
-    line["forms"] = _round(line["forms"])
+    if main_form is None:
+        print(json.dumps({"forms": _round(forms)}), flush=True)
+        return
+    line = {
+        "metric": METRIC,
+        "value": main_form["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": main_form["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[prec],
+        "data": "synthetic",
+        "config": {"workload": "rising_bubble_128x512x128", "cells": 128 * 512 * 128,
+                   "lattices": "D3Q15+D3Q27", "collision": "mrt", "storage": prec,
+                   "streaming": "two buffers, pull, phase field fused into the step",
+                   "boundaries": "bounce-back on all faces",
+                   "timing": f"median of {R} runs of {K} steps"},
+        "roofline": main_form["roofline"],
+        "step_effective_frac": main_form["effective_frac"],
+        "ms_per_step_range": main_form["ms_per_step_range"],
+        "cpu_baseline": cpu,
+        "forms": _round(forms),
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -151,8 +151,11 @@ pflbm_status pflbm_destroy(pflbm_ctx* ctx);
 
 /* Validates and sets the physical parameters (tau > 1/2, M > 0, xi > 0,
  * sigma >= 0, rho > 0, 0 < s_high < 2, normal_eps > 0, s_bulk = 0 or in
- * (0, 2), rho_g_ref finite).  Takes effect for the
- * next step. */
+ * (0, 2), rho_g_ref finite).  Takes effect for the next step.  With FP16
+ * storage, fp16_scale_log2 is part of the stored state's encoding: once the
+ * state is initialised (or loaded) a different value returns PFLBM_ERR_STATE
+ * and changes nothing; saved states must be loaded into contexts with the
+ * scale they were written with. */
 pflbm_status pflbm_set_params(pflbm_ctx* ctx, const pflbm_params* params);
 
 /* Copies an N-byte solid mask (1 = solid, 0 = fluid) into the workspace
@@ -250,8 +253,8 @@ int32_t pflbm_phase_q(void);
 
 /* ---------------------------------------------------------------------------
  * Reverse mode (adjoint) of the step, for gradients of a loss of the phase
- * field with respect to the mobility M, the surface tension sigma and the
- * initial phase field phi0.  The adjoint state lambda holds dL/dh and dL/dg of
+ * field with respect to the mobility M, the surface tension sigma, the
+ * interface width xi and the initial phase field phi0.  The adjoint state lambda holds dL/dh and dL/dg of
  * one time level.  Arithmetic is FP64 for PFLBM_FP64 contexts and FP32
  * otherwise; the parameter gradients are accumulated in FP64.  With FP16S
  * storage the quantisation is treated as the identity.
@@ -281,8 +284,32 @@ pflbm_status pflbm_adjoint_step(pflbm_ctx* ctx, const void* d_state_n, int64_t n
  * the velocity the state was initialised with; zero in solids. */
 pflbm_status pflbm_adjoint_init(pflbm_ctx* ctx, const double* d_u0, double* d_dphi0);
 
-/* out_host = {dL/dM, dL/dsigma} accumulated since attach/reset.  Waits. */
-pflbm_status pflbm_adjoint_grads(pflbm_ctx* ctx, double out_host[2]);
+/* out_host = {dL/dM, dL/dsigma, dL/dxi} accumulated since attach/reset (the
+ * mobility, surface tension and interface width of sec. "Conservative
+ * Allen-Cahn model": M sets the phase-field relaxation, eq. pflbm-tau; sigma
+ * and xi set the chemical potential's beta = 12 sigma/xi and kappa =
+ * 3 sigma xi/2, and xi the counter-term 4 phi (1 - phi)/xi).  dL/dxi holds phi0
+ * fixed: a phi0 built from xi adds dL/dphi0 . dphi0/dxi.  Waits for the
+ * stream. */
+pflbm_status pflbm_adjoint_grads(pflbm_ctx* ctx, double out_host[3]);
+
+/* ---------------------------------------------------------------------------
+ * Measurement helper (not part of the method): the HBM ceiling of a kernel
+ * that only streams data.  Copies `bytes` from d_src to d_dst (device memory,
+ * both 16-byte aligned, not overlapping, bytes a multiple of 16) on
+ * hip_stream, asynchronously, with one of these kernels:
+ *   PFLBM_COPY_W4          4-byte accesses, 8 per thread, non-temporal
+ *   PFLBM_COPY_W16         16-byte accesses, 4 per thread, non-temporal
+ *   PFLBM_COPY_W16_CACHED  16-byte accesses, 4 per thread, cached
+ *   PFLBM_COPY_SOA43       the step kernel's access pattern without its
+ *                          arithmetic: bytes = 43 rows of N floats (42
+ *                          populations + the phase field); one thread per cell
+ *                          loads its 43 values (cached, all in flight) and
+ *                          stores them to the same rows of d_dst (non-temporal)
+ * Returns PFLBM_ERR_ARG for a bad pointer, size or form (nothing enqueued).
+ * ------------------------------------------------------------------------- */
+enum { PFLBM_COPY_W4 = 0, PFLBM_COPY_W16 = 1, PFLBM_COPY_W16_CACHED = 2, PFLBM_COPY_SOA43 = 3 };
+pflbm_status pflbm_hbm_copy(const void* d_src, void* d_dst, size_t bytes, int32_t form, void* hip_stream);
 
 const char* pflbm_status_string(pflbm_status s);
 const char* pflbm_last_error(const pflbm_ctx* ctx);

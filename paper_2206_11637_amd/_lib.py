@@ -15,6 +15,7 @@ COLLISIONS = {"bgk": 0, "mrt": 1}
 STREAMING = {"ab": 0, "aa": 1}
 FORCING = {"first": 0, "guo": 1}
 STATES_WRITE_SRC_PHI, STATES_SKIP_DST_PHI = 1, 2
+COPY_FORMS = {"w4": 0, "w16": 1, "w16_cached": 2, "soa43": 3}
 
 
 class Desc(C.Structure):
@@ -62,6 +63,7 @@ SIGNATURES = {
     "pflbm_adjoint_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "pflbm_adjoint_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pflbm_adjoint_grads": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "pflbm_hbm_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]),
     "pflbm_status_string": (C.c_char_p, [C.c_int]),
     "pflbm_last_error": (C.c_char_p, [C.c_void_p]),
 }

@@ -16,7 +16,7 @@
 //                the forward cell arithmetic from the saved primal state, and
 //                apply its vector-Jacobian product; writes lam^n, the stencil
 //                adjoints s(x) = (dL/d grad phi, dL/d lap phi) and FP64 block
-//                sums of dL/domega_phi and dL/dsigma.
+//                sums of dL/domega_phi, dL/dsigma and dL/dxi.
 //   k_adj_stencil  (z-marching like the forward step)
 //                a_phi^n(y) = sum over valid neighbours m of
 //                -3 w_m c_m . (s_G(y + c_m) + s_G(y)) + 6 w_m (s_L(y + c_m) - s_L(y)),
@@ -36,6 +36,7 @@ template <typename R>
 struct AdjConst {
   R beta4_per_sigma;   // 48 / xi  (0 if xi = inf)
   R kappa_per_sigma;   // 3 xi / 2 (0 if xi = inf)
+  R inv_xi;            // 1 / xi   (0 if xi = inf)
 };
 
 // d(H_i : A)/dA for the symmetric storage xx yy zz xy xz yz (off-diagonals
@@ -67,13 +68,16 @@ __device__ __forceinline__ R second_moment_t(Dir d, const Sym<R>& L) {
 // Vector-Jacobian product of one cell's collision (S1-S15).  lh, lg: in =
 // adjoints of the post-collision populations, out = adjoints of the
 // pre-collision ones (the cell-local part).  Outputs the adjoints of the
-// stencil inputs (grad phi, lap phi) and of omega_phi and sigma.  BULK: the
+// stencil inputs (grad phi, lap phi) and of omega_phi, sigma and xi (xi enters
+// through theta = 4 phi (1 - phi)/xi, beta = 12 sigma/xi and kappa = 3 sigma
+// xi/2, so dtheta/dxi = -theta/xi and dmu/dxi = -(4 beta p3c + kappa lap)/xi
+// with p3c = phi (phi - 1)(phi - 1/2)).  BULK: the
 // bulk mode of g relaxes at P.s_bulk (MRT only); GUO: Guo's full source.
 template <typename R, bool MRT, bool BULK, bool GUO>
 __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R Gx, R Gy, R Gz,
                                          R lap, const Phys<R>& P, const AdjConst<R>& K,
                                          R (&lh)[Q_H], R (&lg)[Q_G], R& lGx, R& lGy, R& lGz,
-                                         R& lL, R& l_omphi, R& l_sigma) {
+                                         R& lL, R& l_omphi, R& l_sigma, R& l_xi) {
   // ---------------- forward recomputation ----------------
   const R phi = sum_h(h);
   const R rho = P.rho_L + phi * P.drho;
@@ -371,6 +375,7 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   l_phi += l_mu * P.beta4 * (R(3) * phi * phi - R(3) * phi + R(0.5));
   lL = -P.kappa * l_mu;
   l_sigma = l_mu * (K.beta4_per_sigma * p3c - K.kappa_per_sigma * lap);
+  l_xi = -K.inv_xi * (l_theta * theta + l_mu * (P.beta4 * p3c + P.kappa * lap));
   // n = G rn
   const R Gln = Gx * lnx + Gy * lny + Gz * lnz;
   const R rn3 = rn * rn * rn;
@@ -423,7 +428,7 @@ struct AdjArgs {
   R* lh_out;
   R* lg_out;
   S4<R>* sadj;      // [N]: dL/d(grad phi x, y, z), dL/d(lap phi)
-  double* gsum;     // [nblocks][2] running sums of dL/domega_phi, dL/dsigma
+  double* gsum;     // [nblocks][3] running sums of dL/domega_phi, dL/dsigma, dL/dxi
   Geom geo;
   Phys<R> P;
   AdjConst<R> K;
@@ -443,7 +448,7 @@ void k_adj_cell(AdjArgs<S> a) {
   using R = typename St::R;
   extern __shared__ unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
-  __shared__ double red[4][2];
+  __shared__ double red[4][3];
   const Geom& G = a.geo;
   const int TX = G.bx + 2, TY = G.by + 2;
   const TileCoord t = tile_of_block(G);
@@ -451,7 +456,7 @@ void k_adj_cell(AdjArgs<S> a) {
   __syncthreads();
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int x = t.x0 + lx, y = t.y0 + ly, z = t.z;
-  double acc0 = 0.0, acc1 = 0.0;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
   if (x < G.nx && y < G.ny && tile[(TY + ly + 1) * TX + lx + 1] != sentinel<R>()) {
     const unsigned idx = x + (unsigned)G.nx * (y + (unsigned)G.ny * z);
     const unsigned walls = wall_bits(tile, TX, TY, lx, ly);
@@ -488,8 +493,9 @@ void k_adj_cell(AdjArgs<S> a) {
       if (i && !(walls & (1u << nb27(d.x, d.y, d.z)))) off = pair_off<R>(i, nb.at(d.x, d.y, d.z), NS);
       lg[i] = *reinterpret_cast<const R*>(pair_base(a.lg_in, G.N, i) + off);
     }
-    R lGx, lGy, lGz, lL, lomp, lsig;
-    cell_vjp<R, MRT, BULK, GUO>(h, g, Gx, Gy, Gz, lap, a.P, a.K, lh, lg, lGx, lGy, lGz, lL, lomp, lsig);
+    R lGx, lGy, lGz, lL, lomp, lsig, lxi;
+    cell_vjp<R, MRT, BULK, GUO>(h, g, Gx, Gy, Gz, lap, a.P, a.K, lh, lg, lGx, lGy, lGz, lL, lomp, lsig,
+                                lxi);
 #pragma unroll
     for (int i = 0; i < Q_H; ++i) *slot(a.lh_out, G.N, i, idx) = lh[i];
 #pragma unroll
@@ -497,22 +503,25 @@ void k_adj_cell(AdjArgs<S> a) {
     a.sadj[idx] = S4<R>{lGx, lGy, lGz, lL};
     acc0 = double(lomp);
     acc1 = double(lsig);
+    acc2 = double(lxi);
   }
   // FP64 block sums in a fixed order, added to this block's running slot
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     acc0 += __shfl_xor(acc0, off, 64);
     acc1 += __shfl_xor(acc1, off, 64);
+    acc2 += __shfl_xor(acc2, off, 64);
   }
   const int tid = threadIdx.x + threadIdx.y * G.bx;
   if ((tid & 63) == 0) {
     red[tid >> 6][0] = acc0;
     red[tid >> 6][1] = acc1;
+    red[tid >> 6][2] = acc2;
   }
   __syncthreads();
-  if (tid < 2) {
+  if (tid < 3) {
     const double v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-    a.gsum[(long long)blockIdx.x * 2 + tid] += v;
+    a.gsum[(long long)blockIdx.x * 3 + tid] += v;
   }
 }
 

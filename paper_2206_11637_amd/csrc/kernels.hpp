@@ -449,6 +449,21 @@ __device__ __forceinline__ typename Store<S>::R rebase(int i, typename Store<S>:
   return Store<S>::kShift ? v + R(wh(i)) * (phi_ref - pl.reader(i, self)) : v;
 }
 
+// p + n for a per-lane global-memory address, which the compiler must take as
+// a new value: the stores of one cell then walk its populations with one
+// 64-bit add each, instead of keeping 41 population offsets (i * N) live in
+// scalar registers, which spill into vector registers and cost two lane reads
+// per store.  Measured on the rising-bubble lattice: FP32 step -1.7 %, FP64
+// -0.3 %, FP16 storage +3.6 % (it then re-reads the stencil planes from LDS
+// for the shift of each h), so the FP16 form keeps the per-population bases.
+template <typename T>
+__device__ __forceinline__ T* next_row(T* p, long long n) {
+  using GT = __attribute__((address_space(1))) T;
+  GT* g = (GT*)(p + n);
+  asm volatile("" : "+v"(g));
+  return (T*)g;
+}
+
 // Two buffers: post-collision values into the cell's own slots.
 template <typename S, bool NT>
 __device__ __forceinline__ void store_own(S* __restrict__ H, S* __restrict__ Gp, long long N,
@@ -458,11 +473,26 @@ __device__ __forceinline__ void store_own(S* __restrict__ H, S* __restrict__ Gp,
                                           const typename Store<S>::R (&h)[Q_H],
                                           const typename Store<S>::R (&g)[Q_G]) {
   using St = Store<S>;
+  if constexpr (sizeof(S) == 2) {
 #pragma unroll
-  for (int i = 0; i < Q_H; ++i)
-    St::template st<NT>(slot(H, N, i, idx), rebase<S>(i, h[i], phi_ref, self, pl), cd.scale_h);
+    for (int i = 0; i < Q_H; ++i)
+      St::template st<NT>(slot(H, N, i, idx), rebase<S>(i, h[i], phi_ref, self, pl), cd.scale_h);
 #pragma unroll
-  for (int i = 0; i < Q_G; ++i) St::template st<NT>(slot(Gp, N, i, idx), g[i], cd.scale_g);
+    for (int i = 0; i < Q_G; ++i) St::template st<NT>(slot(Gp, N, i, idx), g[i], cd.scale_g);
+  } else {
+    S* p = next_row(H, (long long)idx);
+#pragma unroll
+    for (int i = 0; i < Q_H; ++i) {
+      St::template st<NT>(p, rebase<S>(i, h[i], phi_ref, self, pl), cd.scale_h);
+      if (i + 1 < Q_H) p = next_row(p, N);
+    }
+    p = next_row(Gp, (long long)idx);
+#pragma unroll
+    for (int i = 0; i < Q_G; ++i) {
+      St::template st<NT>(p, g[i], cd.scale_g);
+      if (i + 1 < Q_G) p = next_row(p, N);
+    }
+  }
 }
 
 // AA: post-collision values into the slots of the parity's write rule.
@@ -946,6 +976,12 @@ __global__ __launch_bounds__(256) void k_init(InitArgs<S> a) {
     S* q = reinterpret_cast<S*>(pair_base(a.g, G.N, i) + read_off<S, true, RULE>(i, idx, nb, walls, NS));
     St::st(q, v, a.cd.scale_g);
   }
+}
+
+// zero n 16-byte words (grid-stride)
+__global__ __launch_bounds__(256) void k_zero16(uint4* __restrict__ p, size_t n) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = make_uint4(0, 0, 0, 0);
 }
 
 // FP64 phi0 -> compute precision (zero in solids)

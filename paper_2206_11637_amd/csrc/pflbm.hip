@@ -6,6 +6,7 @@
 // library never allocates device memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -15,6 +16,7 @@
 #include "../../include/pflbm.h"
 #include "adjoint.hpp"
 #include "kernels.hpp"
+#include "probe.hpp"
 
 using namespace pflbm;
 
@@ -138,8 +140,8 @@ AdjLayout make_adj_layout(const pflbm_desc* d, const Layout& L) {
   for (int k = 0; k < 2; ++k) { A.off_lg[k] = o; o = align_up(o + A.bytes_lg); }
   for (int k = 0; k < 2; ++k) { A.off_aphi[k] = o; o = align_up(o + A.bytes_aphi); }
   A.off_as = o; o = align_up(o + A.bytes_as);
-  A.off_part = o; o = align_up(o + (size_t)L.nblocks * 2 * sizeof(double));
-  A.off_gsum = o; o = align_up(o + (size_t)L.nblocks * 2 * sizeof(double));
+  A.off_part = o; o = align_up(o + (size_t)L.nblocks * 3 * sizeof(double));
+  A.off_gsum = o; o = align_up(o + (size_t)L.nblocks * 3 * sizeof(double));
   A.off_red = o; o = align_up(o + 8 * sizeof(double));
   A.total = o;
   return A;
@@ -632,11 +634,11 @@ pflbm_status do_save_state(pflbm_ctx* c, void* dst) {
   return check_hip(c, e, "pflbm_save_state");
 }
 
+// FP64 sums of the current state into `red` (5 doubles) through the per-block
+// partials `part` (nblocks x 5 doubles), then to the host.
 template <typename S>
-pflbm_status do_reduce(pflbm_ctx* c, double* out_host) {
+pflbm_status do_reduce_via(pflbm_ctx* c, double* part, double* red, double* out_host) {
   LightArgs<S> a = light_args<S>(c);
-  double* part = reinterpret_cast<double*>(c->ws + c->L.off_part);
-  double* red = reinterpret_cast<double*>(c->ws + c->L.off_red);
   a.partials = part;
   launch_light<S, LM_REDUCE>(c, a, state_rule(c, c->steps));
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->stream, part, c->L.nblocks, 5, red);
@@ -650,6 +652,12 @@ pflbm_status do_reduce(pflbm_ctx* c, double* out_host) {
   for (int k = 0; k < 5; ++k)
     if (!std::isfinite(out_host[k])) return fail(c, PFLBM_ERR_UNSTABLE, "non-finite reduction");
   return PFLBM_OK;
+}
+
+template <typename S>
+pflbm_status do_reduce(pflbm_ctx* c, double* out_host) {
+  return do_reduce_via<S>(c, reinterpret_cast<double*>(c->ws + c->L.off_part),
+                          reinterpret_cast<double*>(c->ws + c->L.off_red), out_host);
 }
 
 #define DISPATCH(c, fn, ...)                                     \
@@ -736,6 +744,13 @@ pflbm_status pflbm_set_params(pflbm_ctx* c, const pflbm_params* p) {
   if (!c) return PFLBM_ERR_ARG;
   std::string why;
   if (pflbm_status s = params_ok(p, why)) return fail(c, s, why);
+  // the stored FP16 populations are scaled by 2^k: a new k would silently
+  // rescale the state (and saved states) by 2^(k_old - k_new)
+  if (c->d.precision == PFLBM_FP32_FP16S && c->initialised &&
+      (p->fp16_scale_log2[0] != c->p.fp16_scale_log2[0] || p->fp16_scale_log2[1] != c->p.fp16_scale_log2[1]))
+    return fail(c, PFLBM_ERR_STATE,
+                "fp16_scale_log2 cannot change once the FP16-storage state is initialised "
+                "(initialise again with the new scale)");
   c->p = *p;
   return PFLBM_OK;
 }
@@ -873,6 +888,50 @@ pflbm_status pflbm_lattice(int32_t q, int32_t* c_out, double* w_out) {
 }
 
 int32_t pflbm_phase_q(void) { return Q_H; }
+
+pflbm_status pflbm_hbm_copy(const void* d_src, void* d_dst, size_t bytes, int32_t form, void* hip_stream) {
+  if (!d_src || !d_dst || d_src == d_dst || bytes == 0) return PFLBM_ERR_ARG;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(d_src) | reinterpret_cast<uintptr_t>(d_dst);
+  if ((a % 16) != 0 || (bytes % 16) != 0) return PFLBM_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const dim3 blk(256);
+  auto grid = [](long long n, int per_block) { return dim3((unsigned)((n + per_block - 1) / per_block)); };
+  switch (form) {
+    case PFLBM_COPY_W4: {
+      const long long n = (long long)(bytes / 4);
+      if ((n + 2047) / 2048 >= (1ll << 31)) return PFLBM_ERR_ARG;
+      hipLaunchKernelGGL((k_copy_lines<unsigned, 8, true>), grid(n, 2048), blk, 0, s,
+                         static_cast<const unsigned*>(d_src), static_cast<unsigned*>(d_dst), n);
+      break;
+    }
+    case PFLBM_COPY_W16: {
+      const long long n = (long long)(bytes / 16);
+      if ((n + 1023) / 1024 >= (1ll << 31)) return PFLBM_ERR_ARG;
+      hipLaunchKernelGGL((k_copy_lines<u32x4, 4, true>), grid(n, 1024), blk, 0, s,
+                         static_cast<const u32x4*>(d_src), static_cast<u32x4*>(d_dst), n);
+      break;
+    }
+    case PFLBM_COPY_W16_CACHED: {
+      const long long n = (long long)(bytes / 16);
+      if ((n + 1023) / 1024 >= (1ll << 31)) return PFLBM_ERR_ARG;
+      hipLaunchKernelGGL((k_copy_lines<u32x4, 4, false>), grid(n, 1024), blk, 0, s,
+                         static_cast<const u32x4*>(d_src), static_cast<u32x4*>(d_dst), n);
+      break;
+    }
+    case PFLBM_COPY_SOA43: {
+      // 43 rows of N floats on each side
+      if (bytes % (43 * 4) != 0) return PFLBM_ERR_ARG;
+      const long long N = (long long)(bytes / (43 * 4));
+      if ((N + 255) / 256 >= (1ll << 31)) return PFLBM_ERR_ARG;
+      hipLaunchKernelGGL((k_copy_soa<42>), grid(N, 256), blk, 0, s, static_cast<const float*>(d_src),
+                         static_cast<float*>(d_dst), N);
+      break;
+    }
+    default:
+      return PFLBM_ERR_ARG;
+  }
+  return hipGetLastError() == hipSuccess ? PFLBM_OK : PFLBM_ERR_HIP;
+}
 
 const char* pflbm_status_string(pflbm_status s) {
   switch (s) {

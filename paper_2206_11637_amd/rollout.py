@@ -1,6 +1,6 @@
 """Differentiable rollouts through the library's reverse-mode kernels.
 
-PFLBMRollout maps (phi0, M, sigma) to the interface-amplitude trace
+PFLBMRollout maps (phi0, M, sigma, xi) to the interface-amplitude trace
     a(n) = < sum_y phi^n(x0, y, z) >_z - depth ,   n = K, 2K, ..., N
 (the column-sum elevation probe of the paper's standing-wave tests, sec.
 "Gravity wave" setup).  Its backward runs the adjoint step kernels in reverse
@@ -36,12 +36,12 @@ class RolloutSpec:
     stats: dict = dataclasses.field(default_factory=dict)
 
 
-def _params_with(p, M, sigma):
+def _params_with(p, M, sigma, xi):
     if isinstance(p, dict):
         q = dict(p)
-        q["mobility"], q["sigma"] = M, sigma
+        q["mobility"], q["sigma"], q["xi"] = M, sigma, xi
         return q
-    return dataclasses.replace(p, mobility=M, sigma=sigma)
+    return dataclasses.replace(p, mobility=M, sigma=sigma, xi=xi)
 
 
 def _amplitude(sim, x0, depth):
@@ -51,11 +51,11 @@ def _amplitude(sim, x0, depth):
 
 class PFLBMRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi0, M, sigma, spec: RolloutSpec):
+    def forward(ctx, phi0, M, sigma, xi, spec: RolloutSpec):
         sim = spec.sim
         N, K = spec.nsteps, spec.sample_every
         S = spec.checkpoint_every or max(1, int(math.ceil(math.sqrt(N))))
-        sim.set_params(_params_with(spec.params, float(M), float(sigma)))
+        sim.set_params(_params_with(spec.params, float(M), float(sigma), float(xi)))
         sim.init_equilibrium(phi0.detach(), spec.u0, spec.pstar0)
         ckpt = {0: sim.save_state()}
         trace = []
@@ -72,7 +72,7 @@ class PFLBMRollout(torch.autograd.Function):
         ctx.spec = spec
         ctx.ckpt = ckpt
         ctx.S = S
-        ctx.M, ctx.sigma = float(M), float(sigma)
+        ctx.M, ctx.sigma, ctx.xi = float(M), float(sigma), float(xi)
         spec.stats["checkpoints"] = len(ckpt)
         spec.stats["checkpoint_every"] = S
         return torch.stack(trace)
@@ -84,7 +84,7 @@ class PFLBMRollout(torch.autograd.Function):
         N, K = spec.nsteps, spec.sample_every
         nz, ny, nx = sim.shape
         grad_trace = grad_trace.detach().to(device=sim.device, dtype=torch.float64)
-        sim.set_params(_params_with(spec.params, ctx.M, ctx.sigma))
+        sim.set_params(_params_with(spec.params, ctx.M, ctx.sigma, ctx.xi))
         sim.adjoint_attach()
         sim.adjoint_reset()
         inj = torch.zeros(sim.shape, dtype=torch.float64, device=sim.device)
@@ -117,21 +117,27 @@ class PFLBMRollout(torch.autograd.Function):
                 inject(n + 1)
                 sim.adjoint_step(states[n - a], n)
         dphi0 = sim.adjoint_init(spec.u0)
-        dM, dsig = sim.adjoint_grads()
+        dM, dsig, dxi = sim.adjoint_grads()
         spec.stats["segment_states"] = S
         dev = grad_trace.device
         return (dphi0.reshape(nz, ny, nx), torch.tensor(dM, dtype=torch.float64, device=dev),
-                torch.tensor(dsig, dtype=torch.float64, device=dev), None)
+                torch.tensor(dsig, dtype=torch.float64, device=dev),
+                torch.tensor(dxi, dtype=torch.float64, device=dev), None)
 
 
 def amplitude_rollout(sim, phi0, M, sigma, *, params, nsteps, sample_every, depth, x0=0,
-                      u0=None, pstar0=None, checkpoint_every=None, stats=None):
+                      u0=None, pstar0=None, checkpoint_every=None, stats=None, xi=None):
     """Differentiable amplitude trace (see module docstring).  phi0 is a
-    float64 tensor [nz, ny, nx] on the simulation's device; M and sigma are
-    0-dim float64 tensors.  Returns a float64 tensor of nsteps // sample_every
-    samples."""
+    float64 tensor [nz, ny, nx] on the simulation's device; M, sigma and xi
+    (default: the interface width of params, held fixed) are 0-dim float64
+    tensors.  dL/dxi holds phi0 fixed; a phi0 computed from xi in torch adds
+    its own term through dL/dphi0.  Returns a float64 tensor of
+    nsteps // sample_every samples."""
+    if xi is None:
+        xi = torch.tensor(float(params["xi"] if isinstance(params, dict) else params.xi),
+                          dtype=torch.float64)
     spec = RolloutSpec(sim, params, nsteps, sample_every, depth, x0,
                        None if u0 is None else torch.as_tensor(u0, dtype=torch.float64).to(sim.device),
                        None if pstar0 is None else torch.as_tensor(pstar0, dtype=torch.float64).to(sim.device),
                        checkpoint_every, stats if stats is not None else {})
-    return PFLBMRollout.apply(phi0, M, sigma, spec)
+    return PFLBMRollout.apply(phi0, M, sigma, xi, spec)

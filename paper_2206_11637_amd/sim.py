@@ -26,6 +26,27 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def check_buffer(t, device, name: str, *, numel: Optional[int] = None, dtype=None,
+                 min_bytes: Optional[int] = None) -> torch.Tensor:
+    """Refuse, before any library call, a caller buffer the kernels would
+    read or write out of bounds or misread: not a tensor, on another device,
+    not contiguous, of another dtype, of another length (numel) or smaller
+    than min_bytes.  Raises ValueError; returns t."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.device != torch.device(device):
+        raise ValueError(f"{name}: on {t.device}, the simulation is on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} values, expected {numel}")
+    if min_bytes is not None and t.numel() * t.element_size() < min_bytes:
+        raise ValueError(f"{name}: {t.numel() * t.element_size()} bytes, needs at least {min_bytes}")
+    return t
+
+
 def _params_struct(p) -> Params:
     get = (lambda k: p[k]) if isinstance(p, dict) else (lambda k: getattr(p, k))
     s = Params()
@@ -88,6 +109,7 @@ class Simulation:
             self.set_params(params)
         if solid is not None:
             m = torch.as_tensor(np.asarray(solid, dtype=np.uint8)).reshape(-1).to(self.device)
+            check_buffer(m, self.device, "solid mask", numel=self.N, dtype=torch.uint8)
             self._mask = m
             self._run("pflbm_set_mask", self.lib.pflbm_set_mask, _ptr(m), keep=(m,))
 
@@ -113,9 +135,14 @@ class Simulation:
                 if t is not None:
                     t.record_stream(self.stream)
 
-    def _f64(self, a, shape) -> torch.Tensor:
-        t = torch.as_tensor(a, dtype=torch.float64).to(self.device).reshape(shape).contiguous()
-        return t
+    def _f64(self, a, components: int, name: str) -> torch.Tensor:
+        """FP64 copy (or view) of a field on the simulation's device, flattened;
+        its length must be components * N (1 for scalars, 3 for vectors)."""
+        t = torch.as_tensor(a, dtype=torch.float64).to(self.device).reshape(-1).contiguous()
+        return check_buffer(t, self.device, name, numel=components * self.N)
+
+    def _state_buf(self, t, name: str) -> torch.Tensor:
+        return check_buffer(t, self.device, name, min_bytes=self.state_bytes())
 
     # ---- forward -------------------------------------------------------------
     def set_params(self, p) -> None:
@@ -123,9 +150,9 @@ class Simulation:
         self._run("pflbm_set_params", self.lib.pflbm_set_params, C.byref(s))
 
     def init_equilibrium(self, phi0, u0=None, pstar0=None) -> None:
-        phi = self._f64(phi0, (-1,))
-        u = None if u0 is None else self._f64(u0, (-1,))
-        p = None if pstar0 is None else self._f64(pstar0, (-1,))
+        phi = self._f64(phi0, 1, "phi0")
+        u = None if u0 is None else self._f64(u0, 3, "u0")
+        p = None if pstar0 is None else self._f64(pstar0, 1, "pstar0")
         self._init_keep = (phi, u, p)   # alive until the kernels have read them
         self._run("pflbm_init_equilibrium", self.lib.pflbm_init_equilibrium, _ptr(phi), _ptr(u),
                   _ptr(p), keep=(phi, u, p))
@@ -153,6 +180,7 @@ class Simulation:
     def phi(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if out is None:
             out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        check_buffer(out, self.device, "phi out", numel=self.N, dtype=torch.float64)
         self._run("pflbm_read_phi", self.lib.pflbm_read_phi, _ptr(out), keep=(out,))
         return out
 
@@ -174,16 +202,20 @@ class Simulation:
     def save_state(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if out is None:
             out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        self._state_buf(out, "saved-state buffer")
         self._run("pflbm_save_state", self.lib.pflbm_save_state, _ptr(out), keep=(out,))
         return out
 
     def load_state(self, buf: torch.Tensor, step_count: int) -> None:
+        self._state_buf(buf, "saved state")
         self._run("pflbm_load_state", self.lib.pflbm_load_state, _ptr(buf), int(step_count),
                   keep=(buf,))
 
     def step_states(self, src: torch.Tensor, dst: torch.Tensor, n: int, flags: int = 0) -> None:
         """One step from saved state `src` (level n) into buffer `dst` (level
         n + 1); flags as in pflbm.h (write src's phi, leave dst's phi unformed)."""
+        self._state_buf(src, "source state")
+        self._state_buf(dst, "destination state")
         self._run("pflbm_step_states", self.lib.pflbm_step_states, _ptr(src), _ptr(dst), int(n),
                   int(flags), keep=(src, dst))
 
@@ -208,25 +240,27 @@ class Simulation:
         self._run("pflbm_adjoint_reset", self.lib.pflbm_adjoint_reset)
 
     def adjoint_inject_phi(self, dl_dphi: torch.Tensor) -> None:
-        t = self._f64(dl_dphi, (-1,))
+        t = self._f64(dl_dphi, 1, "dL/dphi")
         self._inj_keep = t
         self._run("pflbm_adjoint_inject_phi", self.lib.pflbm_adjoint_inject_phi, _ptr(t), keep=(t,))
 
     def adjoint_step(self, state_n: torch.Tensor, n: int) -> None:
+        self._state_buf(state_n, "primal state")
         self._run("pflbm_adjoint_step", self.lib.pflbm_adjoint_step, _ptr(state_n), int(n),
                   keep=(state_n,))
 
     def adjoint_init(self, u0=None) -> torch.Tensor:
-        u = None if u0 is None else self._f64(u0, (-1,))
+        u = None if u0 is None else self._f64(u0, 3, "u0")
         out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         self._run("pflbm_adjoint_init", self.lib.pflbm_adjoint_init, _ptr(u), _ptr(out),
                   keep=(u, out))
         return out
 
     def adjoint_grads(self):
-        out = (C.c_double * 2)()
+        """(dL/dM, dL/dsigma, dL/dxi) accumulated since attach/reset."""
+        out = (C.c_double * 3)()
         self._run("pflbm_adjoint_grads", self.lib.pflbm_adjoint_grads, out)
-        return float(out[0]), float(out[1])
+        return float(out[0]), float(out[1]), float(out[2])
 
 
 def from_workload(wl, precision="fp32", collision="mrt", device="cuda:0", params=None,

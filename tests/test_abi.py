@@ -309,3 +309,27 @@ def test_aa_pattern_reads_and_writes_each_slot_once(q):
             r, w = _aa_maps(nx, ny, nz, periodic, solid, c, odd)
             assert len(set(r)) == len(r) == len(fluid_slots) and set(r) == fluid_slots
             assert len(set(w)) == len(w) == len(fluid_slots) and set(w) == fluid_slots
+
+
+def test_binding_refuses_mismatched_buffers_on_the_host():
+    """The binding's buffer checks (run before any library call): wrong
+    length, dtype, device, contiguity or size raise ValueError; matching
+    buffers pass.  CPU tensors stand in for device buffers here."""
+    import torch
+
+    from paper_2206_11637_amd.sim import check_buffer
+    cpu = torch.device("cpu")
+    ok = torch.zeros(10, dtype=torch.float64)
+    assert check_buffer(ok, cpu, "x", numel=10, dtype=torch.float64) is ok
+    bad = [
+        (torch.zeros(9, dtype=torch.float64), dict(numel=10, dtype=torch.float64), "values"),
+        (torch.zeros(10, dtype=torch.float32), dict(numel=10, dtype=torch.float64), "dtype"),
+        (torch.zeros(20, dtype=torch.float64)[::2], dict(numel=10), "contiguous"),
+        (torch.zeros(100, dtype=torch.uint8), dict(min_bytes=101), "bytes"),
+        (ok.numpy(), dict(numel=10), "tensor"),
+    ]
+    for t, kw, word in bad:
+        with pytest.raises(ValueError, match=word):
+            check_buffer(t, cpu, "x", **kw)
+    with pytest.raises(ValueError, match="simulation is on"):
+        check_buffer(ok, torch.device("cuda:0"), "x")

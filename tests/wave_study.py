@@ -20,9 +20,17 @@ p* = 0.  The profile uses the integer column index, so column 0 is the crest.
 The elevation is read both as the phi = 1/2 crossing at column 0 (linear
 interpolation, the paper's PFLBM probe) and as the column sum of phi.
 
+Velocity sets: the paper runs its two-dimensional waves on the D2Q9 pair.  On
+these L x L x 1 lattices (z periodic, in-plane flow) the library's D3Q27-phase
+build evolves exactly as the D2Q9 pair once its populations are summed over
+c_z (tests/test_gpu_d2q9.py), so --phase d3q27 runs the paper's lattices;
+the default D3Q15 phase lattice differs from it only in the MRT relaxation of
+the phase field's zz moment.
+
 Host-side glue only: the time stepping runs in the library; the closed forms
 are the oracle's.  Run as a script for the full study:
-    python tests/wave_study.py [--L 50 100 200 400] [--tmax 80] [--out FILE]
+    python tests/wave_study.py [--L 50 100 200 400] [--tmax 80] [--phase d3q27]
+                               [--out FILE.json] [--table FILE.md]
 """
 from __future__ import annotations
 
@@ -99,14 +107,15 @@ def reference(c, t):
 
 
 def run(kind: str, L: int, tmax: float, precision: str = "fp32", streaming: str = "ab",
-        log=None):
+        log=None, phase: str = "d3q15"):
     """Simulate to t* = tmax; returns times t*, a*(crossing), a*(column sum),
     the analytic a*, and summary errors."""
     import torch
 
     from paper_2206_11637_amd.sim import from_workload
     wl, c = setup(kind, L)
-    sim = from_workload(wl, precision=precision, collision="mrt", streaming=streaming)
+    sim = from_workload(wl, precision=precision, collision="mrt", streaming=streaming,
+                        phase_lattice=phase)
     m0 = sim.reduce()[0]
     every = DT_STAR / c["w0"]
     nsamp = int(round(tmax / DT_STAR))
@@ -129,7 +138,7 @@ def run(kind: str, L: int, tmax: float, precision: str = "fp32", streaming: str 
     ac, asum = np.array(ac), np.array(asum)
     return dict(c, tstar=tstar.tolist(), a_cross=ac.tolist(), a_sum=asum.tolist(),
                 a_ref=ref.tolist(), steps=steps[-1], seconds=time.time() - t0,
-                mass_drift=mass_drift, precision=precision, streaming=streaming,
+                mass_drift=mass_drift, precision=precision, streaming=streaming, phase=phase,
                 **summary(tstar, ac, ref))
 
 
@@ -165,7 +174,10 @@ def main():
                     help="t* limit for L >= 400 (default: --tmax)")
     ap.add_argument("--kinds", nargs="+", default=["gravity", "capillary"])
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--phase", default="d3q15", choices=["d3q15", "d3q27"],
+                    help="phase lattice build (d3q27 on these planar lattices = the D2Q9 pair)")
+    ap.add_argument("--out", default=None, help="JSON with the full traces")
+    ap.add_argument("--table", default=None, help="Markdown table of the summaries")
     args = ap.parse_args()
 
     def log(m):
@@ -176,7 +188,7 @@ def main():
         for L in args.L:
             tmax = args.tmax_large if (args.tmax_large and L >= 400) else args.tmax
             log(f"{kind} wave L={L} to t*={tmax}")
-            r = run(kind, L, tmax, args.precision, log=log)
+            r = run(kind, L, tmax, args.precision, log=log, phase=args.phase)
             log(f"  first minimum t*={r['t_min']:.3f} (ref {r['t_min_ref']:.3f}) "
                 f"a*={r['a_min']:.4f} (ref {r['a_min_ref']:.4f}) rms={r['rms']:.4f} "
                 f"envelope(last quarter)={r['envelope_ratio_last_quarter']:.3f} "
@@ -186,6 +198,29 @@ def main():
             if args.out:
                 with open(args.out, "w") as f:
                     json.dump(res, f)
+            if args.table:
+                write_table(res, args.table, " ".join(sys.argv[1:]))
+
+
+def write_table(res, path, argv):
+    """Markdown table of the runs' summaries (the numbers the study reports)."""
+    lat = {"d3q15": "D3Q15 + D3Q27", "d3q27": "D2Q9 pair (D3Q27 build, planar)"}
+    rows = ["| wave | L | lattices | precision | t* run | steps | first min t* (ref) | "
+            "first min a* (ref) | rms a* | envelope, last quarter | mass drift | GPU s |",
+            "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for r in res:
+        rows.append(f"| {r['kind']} | {r['L']} | {lat[r['phase']]} | {r['precision']} | "
+                    f"{r['tstar'][-1]:.0f} | {r['steps']} | {r['t_min']:.3f} ({r['t_min_ref']:.3f}) | "
+                    f"{r['a_min']:.3f} ({r['a_min_ref']:.3f}) | {r['rms']:.3f} | "
+                    f"{r['envelope_ratio_last_quarter']:.2f} | {r['mass_drift']:.0e} | "
+                    f"{r['seconds']:.0f} |")
+    head = ("# Standing waves on the GPU against their closed forms\n\n"
+            "Written by `python tests/wave_study.py " + argv + "` (elevation at x = 0 from the\n"
+            "phi = 1/2 crossing, a* = a / a0, t* = omega0 t; references: gravity wave with viscous\n"
+            "decay, Prosperetti's capillary wave; envelope = max|a*| over the last quarter of the\n"
+            "run relative to the reference's).\n\n")
+    with open(path, "w") as f:
+        f.write(head + "\n".join(rows) + "\n")
 
 
 if __name__ == "__main__":
