@@ -198,6 +198,19 @@ pflbm_status pflbm_read_populations(pflbm_ctx* ctx, double* d_h, double* d_g);
  * Waits for the stream.  Returns PFLBM_ERR_UNSTABLE if any is NaN/Inf. */
 pflbm_status pflbm_reduce(pflbm_ctx* ctx, double out_host[5]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sums of
+ * pflbm_reduce with its per-block partial sums kept in a static device array
+ * of the library (16 MiB per GPU, held until the process ends) instead of the
+ * context's workspace; same results, bitwise.  Returns PFLBM_ERR_ARG when the
+ * lattice needs more than that: 40 bytes per tile and z plane (tiles of 256
+ * cells, 64 x 4 where nx > 32), rounded up to 256, plus 256, i.e. about
+ * 1.3 MB for 128x512x128 and 8.8 MB for 384^3.  Allocates nothing.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (two host
+ * threads, or contexts on different streams of the same GPU) race.  Waits for
+ * the stream. */
+pflbm_status pflbm_reduce_static(pflbm_ctx* ctx, double out_host[5]);
+
 /* Bytes of one saved state: h [15][N] and g [27][N] in storage precision
  * (layout of the streaming scheme), phi^n [N] and, for the FP32 and FP16S
  * forms, phi^{n-1} [N] (the shift reference; defined on fluid cells). */

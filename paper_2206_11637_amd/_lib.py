@@ -47,6 +47,7 @@ SIGNATURES = {
     "pflbm_read_phi": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pflbm_read_populations": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pflbm_reduce": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "pflbm_reduce_static": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pflbm_state_bytes": (C.c_size_t, [C.c_void_p]),
     "pflbm_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pflbm_load_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),

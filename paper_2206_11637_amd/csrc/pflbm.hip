@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -660,6 +661,43 @@ pflbm_status do_reduce(pflbm_ctx* c, double* out_host) {
                           reinterpret_cast<double*>(c->ws + c->L.off_red), out_host);
 }
 
+// ---- the allocation-free reduction -------------------------------------------
+// pflbm_reduce_static keeps its partial sums in this file-scope device array
+// instead of the context's workspace.  Each GPU holds its own copy, whose
+// address is looked up once per device (hipGetSymbolAddress, with that device
+// current) and kept; in host code the array's name is not a device address.
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// bytes of scratch the reduction of a lattice with this layout needs: one
+// 5-double partial per (tile, plane) block, then the 5 sums
+size_t static_scratch_bytes(const Layout& L) {
+  return align_up((size_t)L.nblocks * 5 * sizeof(double)) + align_up(8 * sizeof(double));
+}
+
+// device address of `scratch` on device dev
+pflbm_status scratch_of(pflbm_ctx* c, int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, PFLBM_ERR_STATE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    if (pflbm_status s = check_hip(c, hipGetDevice(&cur), "pflbm_reduce_static device")) return s;
+    if (cur != dev)
+      if (pflbm_status s = check_hip(c, hipSetDevice(dev), "pflbm_reduce_static set device")) return s;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (pflbm_status s = check_hip(c, e, "pflbm_reduce_static symbol address")) return s;
+    if (!p) return fail(c, PFLBM_ERR_HIP, "pflbm_reduce_static: null scratch address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return PFLBM_OK;
+}
+
 #define DISPATCH(c, fn, ...)                                     \
   do {                                                           \
     switch ((c)->d.precision) {                                  \
@@ -823,6 +861,26 @@ pflbm_status pflbm_reduce(pflbm_ctx* c, double out_host[5]) {
   if (!out_host) return fail(c, PFLBM_ERR_ARG, "output is NULL");
   if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
   DISPATCH(c, do_reduce, c, out_host);
+}
+
+pflbm_status pflbm_reduce_static(pflbm_ctx* c, double out_host[5]) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!out_host) return fail(c, PFLBM_ERR_ARG, "output is NULL");
+  const size_t need = static_scratch_bytes(c->L);
+  if (need > kStaticScratchBytes)
+    return fail(c, PFLBM_ERR_ARG, "pflbm_reduce_static: the lattice needs " + std::to_string(need) +
+                                      " bytes of partial sums, the static scratch holds " +
+                                      std::to_string(kStaticScratchBytes));
+  if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
+  // the device of the context is the device of its workspace
+  hipPointerAttribute_t attr{};
+  if (pflbm_status s = check_hip(c, hipPointerGetAttributes(&attr, c->ws), "pflbm_reduce_static workspace"))
+    return s;
+  char* base = nullptr;
+  if (pflbm_status s = scratch_of(c, attr.device, &base)) return s;
+  double* part = reinterpret_cast<double*>(base);
+  double* red = reinterpret_cast<double*>(base + align_up((size_t)c->L.nblocks * 5 * sizeof(double)));
+  DISPATCH(c, do_reduce_via, c, part, red, out_host);
 }
 
 size_t pflbm_state_bytes(const pflbm_ctx* c) {

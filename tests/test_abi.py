@@ -311,6 +311,30 @@ def test_aa_pattern_reads_and_writes_each_slot_once(q):
             assert len(set(w)) == len(w) == len(fluid_slots) and set(w) == fluid_slots
 
 
+def test_static_reduction_refuses_lattices_beyond_its_scratch():
+    """pflbm_reduce_static rejects, on the host and before touching the GPU, a
+    lattice whose partial sums exceed the 16 MiB static array (1024 x 1024 x
+    256 cells: 4096 tiles x 256 planes x 40 bytes), and names the sizes."""
+    L, lib = _lib()
+    d = L.Desc(1024, 1024, 256, 7, 1, 1, 0)
+    n = lib.pflbm_workspace_bytes(C.byref(d))
+    assert n > 0
+    ctx = C.c_void_p()
+    assert lib.pflbm_create(C.byref(d), C.c_void_p(4096), n, None, C.byref(ctx)) == 0
+    out = (C.c_double * 5)()
+    assert lib.pflbm_reduce_static(ctx, out) == L.PFLBM_ERR_ARG
+    msg = lib.pflbm_last_error(ctx).decode()
+    assert "static scratch" in msg and str(16 << 20) in msg
+    assert lib.pflbm_reduce_static(ctx, None) == L.PFLBM_ERR_ARG
+    assert lib.pflbm_destroy(ctx) == 0
+    # a lattice within the limit gets past the size check to the state check
+    d = L.Desc(384, 384, 384, 5, 1, 1, 0)
+    n = lib.pflbm_workspace_bytes(C.byref(d))
+    assert lib.pflbm_create(C.byref(d), C.c_void_p(4096), n, None, C.byref(ctx)) == 0
+    assert lib.pflbm_reduce_static(ctx, out) == L.PFLBM_ERR_STATE
+    assert lib.pflbm_destroy(ctx) == 0
+
+
 def test_binding_refuses_mismatched_buffers_on_the_host():
     """The binding's buffer checks (run before any library call): wrong
     length, dtype, device, contiguity or size raise ValueError; matching
