@@ -48,7 +48,13 @@ STEP_BYTES_D3Q27 = {"fp64": 880, "fp32": 440, "fp16s": 224}
 # same box (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE), keyed by form; taken for
 # the current kernel (profiles/k_step_hbm_traffic.txt) and re-measured
 # whenever it changes.  Forms without an entry report null.
-TRAFFIC = {}
+TRAFFIC = {"fp64_rising_bubble_128x512x128": 6.0528e9,
+           "fp32_rising_bubble_128x512x128": 3.4070e9,
+           "fp16s_rising_bubble_128x512x128": 1.5512e9,
+           "fp32_d3q27_phase_rising_bubble_128x512x128": 4.2509e9,
+           "fp32_drop_impact_384^3": 2.35292e10,
+           "fp16s_drop_impact_384^3": 1.11293e10,
+           "fp32_in_place_aa_rising_bubble_128x512x128": 3.0628e9}
 TRAFFIC_UNIT = "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
 DTYPE = {"fp32": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64"}
 
@@ -231,14 +237,24 @@ def grad_errors(g, ref):
     return e
 
 
+def column_level(wl, x0):
+    """Initial column sum of phi at x = x0, averaged over z (the probe's value at
+    t = 0): as the probe's depth it makes the samples measure the change."""
+    import numpy as np
+    return float(np.asarray(wl.phi0)[:, :, x0].sum(axis=1).mean())
+
+
 def adjoint_form(wl, precision, nsteps, sample_every, x0, depth, ref_wl=None, ckpt=None):
     """Reverse-mode cost of a form, plus its gradients' relative error against
-    the FP64 form of the same rollout (on ref_wl when the full lattice's FP64
+    the FP64 form of the same rollout (on ref_wl, probed on its axis column
+    x = nx/2 with its own initial level as depth, when the full lattice's FP64
     checkpoints would not fit in HBM)."""
     out, grads = adjoint_run(wl, precision, nsteps, sample_every, x0, depth, ckpt)
     out.update({k: v for k, v in grads.items() if k != "dphi0"})
     rw = ref_wl or wl
     if ref_wl is not None:
+        x0 = rw.nx // 2
+        depth = column_level(rw, x0)
         _, grads = adjoint_run(rw, precision, nsteps, sample_every, x0, depth, ckpt, timed=False)
     _, ref = adjoint_run(rw, "fp64", nsteps, sample_every, x0, depth, ckpt, timed=False)
     out["grad_rel_err_vs_fp64"] = grad_errors(grads, ref)
@@ -480,7 +496,7 @@ def main():
             # the FP64 reference of the gradients runs on the tube at half the
             # resolution (64x512x64), where its checkpoints fit in HBM
             form("adjoint_taylor_bubble_128x1024x128_fp16s", adjoint_form, wl4, "fp16s",
-                 args.adj_steps, 10, 32, 0.0, W.config4(scale=2))
+                 args.adj_steps, 10, 64, column_level(wl4, 64), W.config4(scale=2))
             del wl4
     cpu = None
     if not args.no_cpu_baseline and not only:
