@@ -163,25 +163,37 @@ pflbm_status pflbm_set_params(pflbm_ctx* ctx, const pflbm_params* params);
  * bits from it.  Only for contexts created with has_mask. */
 pflbm_status pflbm_set_mask(pflbm_ctx* ctx, const uint8_t* d_solid);
 
-/* Equilibrium initialisation: h_i = phi0 w_i [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u],
+/* Equilibrium initialisation (sec. "Lattice Boltzmann equations", eq. feq with
+ * rho_0 = 1 for g, and the phase field's equilibrium phi Gamma_i(u) for h; the
+ * initial phase field is the caller's, e.g. the tanh profile of sec.
+ * "Numerical experiments"): h_i = phi0 w_i [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u],
  * g_i = w_i [p*0 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u], zero in solids, then
- * phi = sum_i h_i.  d_phi0 [N], d_u0 [3][N], d_pstar0 [N] (FP64; d_u0 or
- * d_pstar0 may be NULL for zero).  Resets the step counter to 0. */
+ * phi = sum_i h_i (eq. zeroth_moment_phase).  d_phi0 [N], d_u0 [3][N],
+ * d_pstar0 [N] (FP64; d_u0 or d_pstar0 may be NULL for zero).  Resets the
+ * step counter to 0. */
 pflbm_status pflbm_init_equilibrium(pflbm_ctx* ctx, const double* d_phi0,
                                     const double* d_u0, const double* d_pstar0);
 
-/* Advances nsteps >= 0 time steps (collide + stream of h and g, then the phi
- * update), asynchronously.  With a check interval K > 0 (pflbm_set_check_interval)
- * it also reduces sum(phi) and sum(p*) in FP64 every K steps, waits for that
- * result, and stops with PFLBM_ERR_UNSTABLE at the first non-finite one; the
- * step count then names the step after which it was detected. */
+/* Advances nsteps >= 0 time steps, asynchronously.  One step is the coupled
+ * update of sec. "Lattice Boltzmann equations": the phase-field LBE with the
+ * counter-term source (eq. lb_interface, relaxation eq. pflbm-tau), the
+ * hydrodynamic LBE with F = F_s + F_b + F_p + F_mu, both collided with
+ * eq. mrt (or eq. BGK) and streamed (eq. streaming) with halfway bounce-back,
+ * then phi = sum_i h_i (eq. zeroth_moment_phase).  With a check interval
+ * K > 0 (pflbm_set_check_interval) it also reduces sum(phi) and sum(p*) in
+ * FP64 every K steps, waits for that result, and stops with
+ * PFLBM_ERR_UNSTABLE at the first non-finite one; the step count then names
+ * the step after which it was detected. */
 pflbm_status pflbm_step(pflbm_ctx* ctx, int64_t nsteps);
 
 /* Sets the stability check interval K of pflbm_step (0 = never, the
  * default; each check costs one reduction and one host round trip). */
 pflbm_status pflbm_set_check_interval(pflbm_ctx* ctx, int64_t every);
 
-/* Cell moments of the current state as FP64: phi [N], u [3][N] (the
+/* Cell moments of the current state as FP64 (sec. "Lattice Boltzmann
+ * equations": phi = sum_i h_i, eq. zeroth_moment_phase; p* = sum_i g_i,
+ * eq. zeroth_moment_hydro, the pressure being p = p* rho c_s^2; u from the
+ * first moment of g with half the force): phi [N], u [3][N] (the
  * force-corrected velocity u = j + F/(2 rho)), p* [N]; zero in solids.  Any
  * output may be NULL. */
 pflbm_status pflbm_read_moments(pflbm_ctx* ctx, double* d_phi, double* d_u, double* d_pstar);
@@ -193,7 +205,9 @@ pflbm_status pflbm_read_phi(pflbm_ctx* ctx, double* d_phi);
  * d_h [15][N], d_g [27][N] in the library's velocity order (pflbm_lattice). */
 pflbm_status pflbm_read_populations(pflbm_ctx* ctx, double* d_h, double* d_g);
 
-/* FP64 sums over fluid cells: out_host = {sum phi, sum p*, sum j_x, sum j_y,
+/* FP64 sums over fluid cells of the moments of sec. "Lattice Boltzmann
+ * equations" (the phase mass the conservative Allen-Cahn model conserves, the
+ * sum of p* and the momentum): out_host = {sum phi, sum p*, sum j_x, sum j_y,
  * sum j_z} with j = sum_i c_i g_i.  Deterministic (fixed reduction order).
  * Waits for the stream.  Returns PFLBM_ERR_UNSTABLE if any is NaN/Inf. */
 pflbm_status pflbm_reduce(pflbm_ctx* ctx, double out_host[5]);
@@ -267,10 +281,11 @@ int32_t pflbm_phase_q(void);
 /* ---------------------------------------------------------------------------
  * Reverse mode (adjoint) of the step, for gradients of a loss of the phase
  * field with respect to the mobility M, the surface tension sigma, the
- * interface width xi and the initial phase field phi0.  The adjoint state lambda holds dL/dh and dL/dg of
- * one time level.  Arithmetic is FP64 for PFLBM_FP64 contexts and FP32
- * otherwise; the parameter gradients are accumulated in FP64.  With FP16S
- * storage the quantisation is treated as the identity.
+ * interface width xi and the initial phase field phi0.  The adjoint state
+ * lambda holds dL/dh and dL/dg of one time level.  Arithmetic is FP64 for
+ * PFLBM_FP64 contexts and FP32 otherwise; the parameter gradients are
+ * accumulated in FP64.  With FP16S storage the quantisation is treated as the
+ * identity.
  * ------------------------------------------------------------------------- */
 
 /* Bytes of the adjoint workspace for this description (0 if invalid). */
