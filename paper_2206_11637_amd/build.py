@@ -23,6 +23,12 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a * b + c is fused only where it is written as one expression: with the
+    # default (fuse across statements) the compiler's choice of which product
+    # to fuse followed the placement of code in branches, and the two
+    # streaming schemes, or one scheme with and without its fast-wave branch,
+    # stopped giving the same bits
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
 ]
 
