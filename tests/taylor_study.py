@@ -50,6 +50,7 @@ script for the study:
     python tests/taylor_study.py [--D 64 128] [--precision fp64 fp32]
                                  [--gauge mid paper buoyant] [--s-bulk 1] [--every 0.5]
                                  [--tmax 15] [--out FILE]
+    python tests/taylor_study.py --diagnose --D 64 --precision fp32 --every 0.5
 """
 from __future__ import annotations
 
@@ -238,6 +239,137 @@ def run(D: int, precision: str = "fp64", gauge: str = "mid", streaming: str = "a
     return out
 
 
+def field_stats(sim, fluid):
+    """Diagnostics of one state: the phase field's range over fluid cells, and
+    max |u| with its cell and the p* range in the gas (phi < 1/2) and in the
+    liquid."""
+    import torch
+    phi, u, ps = sim.moments()
+    umag = torch.sqrt((u * u).sum(0))
+    gas = fluid & (phi < 0.5)
+    liq = fluid & (phi >= 0.5)
+    out = dict(phi_min=float(phi[fluid].min()), phi_max=float(phi[fluid].max()))
+    for name, m in (("gas", gas), ("liquid", liq)):
+        um = torch.where(m, umag, torch.zeros_like(umag))
+        k = int(torch.argmax(um))
+        nz, ny, nx = phi.shape
+        out[f"umax_{name}"] = float(um.reshape(-1)[k])
+        out[f"umax_{name}_cell"] = (k % nx, (k // nx) % ny, k // (nx * ny))
+        out[f"pstar_{name}"] = (float(ps[m].min()), float(ps[m].max()))
+    del phi, u, ps, umag
+    return out
+
+
+def force_terms(sim, wl, cell, half=3):
+    """The four force terms of the cells around `cell` (x, y, z): the state's
+    populations are read back and the oracle's collision is evaluated on a
+    (2 half + 1)^3 window (walls at its faces, so only the inner cells are
+    exact).  Returns the largest |F_s|, |F_b|, |F_p|, |F_mu| and |u| over the
+    window's inner cube, and phi, p* at the cell itself."""
+    import torch
+
+    from gpu_util import gpu_pops_oracle_order
+    from oracle import pflbm as OP
+    h, g = gpu_pops_oracle_order(sim)
+    nz, ny, nx = wl.nz, wl.ny, wl.nx
+    x, y, z = cell
+    xs = slice(max(x - half, 0), min(x + half + 1, nx))
+    ys = slice(max(y - half, 0), min(y + half + 1, ny))
+    zs = slice(max(z - half, 0), min(z + half + 1, nz))
+    hw = h.reshape(h.shape[0], nz, ny, nx)[:, zs, ys, xs].reshape(h.shape[0], -1).clone()
+    gw = g.reshape(27, nz, ny, nx)[:, zs, ys, xs].reshape(27, -1).clone()
+    del h, g
+    sol = wl.solid[zs, ys, xs]
+    grid = OP.Grid(sol.shape[2], sol.shape[1], sol.shape[0], (False, False, False), sol)
+    prm = OP.OracleParams.from_workload(wl.params, "mrt")
+    _, _, aux = OP.collide(grid, prm, hw, gw)
+    drho = prm.rho_H - prm.rho_L
+    Fs = aux["mu"][None] * aux["grad"]
+    Fb = (aux["rho"] - prm.rho_g_ref)[None] * torch.tensor(prm.g, dtype=torch.float64)[:, None]
+    Fp = -(aux["pstar"] * drho / 3.0)[None] * aux["grad"]
+    Fmu = aux["F"] - Fs - Fb - Fp
+    shp = sol.shape
+    inner = torch.zeros(shp, dtype=torch.bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    inner &= ~torch.as_tensor(sol)
+    inner = inner.reshape(-1)
+
+    def mx(v):
+        return float(torch.sqrt((v * v).sum(0))[inner].max())
+    c = ((z - zs.start) * shp[1] + (y - ys.start)) * shp[2] + (x - xs.start)
+    return dict(F_s=mx(Fs), F_b=mx(Fb), F_p=mx(Fp), F_mu=mx(Fmu), u=mx(aux["u"]),
+                phi=float(aux["phi"][c]), pstar=float(aux["pstar"][c]))
+
+
+def diagnose(D: int, precision: str = "fp32", tmax: float = 15.0, every: float = 0.5, log=print):
+    """Run to t* = tmax recording field_stats every `every`; if the run turns
+    non-finite, step again one step at a time from the last finite sample to
+    the first step with a non-finite phase field, and report the statistics of
+    the steps before it and the force terms around the cell where the
+    velocity peaks."""
+    import torch
+
+    from paper_2206_11637_amd.sim import from_workload
+    wl, c = setup(D)
+    fluid = torch.as_tensor(~wl.solid, device="cuda:0")
+    sim = from_workload(wl, precision=precision, collision="mrt")
+    samples, done, last_ok = [], 0, None
+    nsamp = int(round(tmax / every))
+    bad_at = None
+    for i in range(nsamp + 1):
+        s = int(round(i * every * c.t_ref))
+        if s > done:
+            sim.step(s - done)
+        done = s
+        if not bool(torch.isfinite(sim.phi()).all()):
+            bad_at = s
+            break
+        st = field_stats(sim, fluid)
+        st.update(tstar=i * every, step=s)
+        samples.append(st)
+        last_ok = (s, sim.save_state())
+        log(f"  t*={i * every:5.2f} step {s:6d} phi [{st['phi_min']:+.3f}, {st['phi_max']:.3f}] "
+            f"|u|max gas {st['umax_gas']:.3e} at {st['umax_gas_cell']} liquid {st['umax_liquid']:.3e} "
+            f"p* gas [{st['pstar_gas'][0]:+.3f}, {st['pstar_gas'][1]:+.3f}] "
+            f"liquid [{st['pstar_liquid'][0]:+.3f}, {st['pstar_liquid'][1]:+.3f}]")
+    out = dict(D=D, precision=precision, samples=samples, first_nonfinite_step=None)
+    if bad_at is None:
+        return out
+    s0, buf = last_ok
+    sim.load_state(buf, s0)
+    steps = []
+    n = s0
+    while n < bad_at:
+        st = field_stats(sim, fluid)
+        st.update(step=n, tstar=n / c.t_ref)
+        steps.append(st)
+        sim.step(1)
+        n += 1
+        if not bool(torch.isfinite(sim.phi()).all()):
+            break
+    out["first_nonfinite_step"] = n
+    out["first_nonfinite_tstar"] = n / c.t_ref
+    out["last_steps"] = steps[-20:]
+    log(f"  first non-finite phase field after step {n} (t* = {n / c.t_ref:.3f})")
+    for st in steps[-8:]:
+        log(f"    step {st['step']}: |u|max gas {st['umax_gas']:.3e} at {st['umax_gas_cell']} "
+            f"liquid {st['umax_liquid']:.3e} at {st['umax_liquid_cell']} "
+            f"p* gas [{st['pstar_gas'][0]:+.3f}, {st['pstar_gas'][1]:+.3f}]")
+    # force terms around the peak velocity a few steps before the fault
+    back = max(s0, n - 6)
+    sim.load_state(buf, s0)
+    if back > s0:
+        sim.step(back - s0)
+    st = field_stats(sim, fluid)
+    for name in ("gas", "liquid"):
+        cell = st[f"umax_{name}_cell"]
+        f = force_terms(sim, wl, cell)
+        out[f"forces_step{back}_{name}_peak"] = dict(cell=cell, **f)
+        log(f"  step {back}, peak |u| in the {name} at {cell}: " +
+            " ".join(f"{k} {v:.3e}" if isinstance(v, float) else f"{k} {v}" for k, v in f.items()))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--D", type=int, nargs="+", default=[64, 128])
@@ -248,10 +380,19 @@ def main():
     ap.add_argument("--every", type=float, default=0.5)
     ap.add_argument("--phase-lattice", default="d3q15", choices=["d3q15", "d3q27"])
     ap.add_argument("--out", default=None)
+    ap.add_argument("--diagnose", action="store_true",
+                    help="per-sample diagnostics and the first non-finite step (first --D, --precision)")
     args = ap.parse_args()
 
     def log(m):
         print(m, flush=True)
+
+    if args.diagnose:
+        r = diagnose(args.D[0], args.precision[0], args.tmax, args.every, log)
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(r, f)
+        return
 
     res = []
     for D in args.D:

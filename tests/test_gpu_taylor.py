@@ -2,12 +2,17 @@
 through the library, against the Reynolds number the paper reports for its
 PFLBM at that resolution (26.83).  Setup and readings in tests/taylor_study.py.
 
-At D = 64 the run here turns non-finite between t* = 14 and 15 (the gas,
-with a kinematic viscosity of 0.004 lattice units and a 744:1 density ratio,
-circulates at up to ~0.1 inside the bubble), so the test measures the rise
-velocity over t* = 10 to 14, where the rise is already steady (Re 26.20 from
-the gas region's centre of mass); the paper's window t* = 10 to 15 is met at
-D = 128 by the study script (Re 26.55 against the paper's 27.12, FP32)."""
+At D = 64 the run here turns non-finite between t* = 14 and 15, so the test
+measures the rise velocity over t* = 10 to 14, where the rise is already
+steady (Re 26.20 from the gas region's centre of mass); the paper's window
+t* = 10 to 15 is met at D = 128 by the study script (Re 26.55 against the
+paper's 27.12, FP32).  Where the D = 64 run fails (taylor_study.py
+--diagnose, tests/results/taylor_d64_divergence.md): from t* ~ 13.5 the gas's
+circulation grows (peak speed 0.09 -> 0.18, gas p* range threefold), and at
+t* = 14.55 one gas cell whose phase field has undershot to -7.7e-4 (density
+rho(phi) a quarter of rho_L) is accelerated by the pressure force F_p, 13x
+the other forces there, to |u| = 47 within six steps; clamping phi in
+rho(phi) and tau(phi) does not carry the run further."""
 import pytest
 
 from gpu_util import say
