@@ -244,7 +244,8 @@ def column_level(wl, x0):
     return float(np.asarray(wl.phi0)[:, :, x0].sum(axis=1).mean())
 
 
-def adjoint_form(wl, precision, nsteps, sample_every, x0, depth, ref_wl=None, ckpt=None):
+def adjoint_form(wl, precision, nsteps, sample_every, x0, depth, ref_wl=None, ckpt=None,
+                 conditioning=False):
     """Reverse-mode cost of a form, plus its gradients' relative error against
     the FP64 form of the same rollout (on ref_wl, probed on its axis column
     x = nx/2 with its own initial level as depth, when the full lattice's FP64
@@ -259,6 +260,21 @@ def adjoint_form(wl, precision, nsteps, sample_every, x0, depth, ref_wl=None, ck
     _, ref = adjoint_run(rw, "fp64", nsteps, sample_every, x0, depth, ckpt, timed=False)
     out["grad_rel_err_vs_fp64"] = grad_errors(grads, ref)
     out["grad_rel_err_lattice"] = rw.name
+    if conditioning:
+        # the FP64 gradients' own change when phi0 moves by 1e-7 relative (an
+        # FP32 rounding): where it is of the order of the error above, that
+        # gradient is ill-conditioned on this rollout, not lost by the form
+        import dataclasses
+
+        import numpy as np
+
+        import workloads as W
+        rng = np.random.default_rng(W.SEED + 2)
+        fluid = np.ones(rw.phi0.shape, bool) if rw.solid is None else ~rw.solid
+        pert = dataclasses.replace(rw, phi0=np.where(
+            fluid, rw.phi0 * (1 + 1e-7 * rng.standard_normal(rw.phi0.shape)), 0.0))
+        _, g_p = adjoint_run(pert, "fp64", nsteps, sample_every, x0, depth, ckpt, timed=False)
+        out["fp64_grad_change_under_1e-7_phi0_perturbation"] = grad_errors(g_p, ref)
     return out
 
 
@@ -478,7 +494,9 @@ def main():
                            wl2.params, wl2.phi0[z0:z0 + 48].copy(), wl2.u0[:, z0:z0 + 48].copy(),
                            wl2.pstar0[z0:z0 + 48].copy(), None, wl2.steps)
         n = "fp32_shard_384x384x48_of_drop_impact"
-        form(n, time_form, n, shard, "fp32", K, Wm, R)
+        # as many steps as the full drop: the cut drop, wrapped in z, turns
+        # non-finite after ~1k steps at M = 0.01
+        form(n, time_form, n, shard, "fp32", half, Wm, R)
         del shard
         del wl2
         if slow:
@@ -496,7 +514,8 @@ def main():
             # the FP64 reference of the gradients runs on the tube at half the
             # resolution (64x512x64), where its checkpoints fit in HBM
             form("adjoint_taylor_bubble_128x1024x128_fp16s", adjoint_form, wl4, "fp16s",
-                 args.adj_steps, 10, 64, column_level(wl4, 64), W.config4(scale=2))
+                 args.adj_steps, 10, 64, column_level(wl4, 64), W.config4(scale=2),
+                 conditioning=True)
             del wl4
     cpu = None
     if not args.no_cpu_baseline and not only:

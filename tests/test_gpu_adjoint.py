@@ -262,8 +262,18 @@ def test_taylor_tube_reduced_precision_gradients_against_fp64():
     respect to sigma, M and xi, 4000 steps with checkpoints) at half the
     resolution, 64x512x64, where the FP64 rollout's checkpoints fit in HBM, with
     the FP32 form beside it.  Loss: the squared change of the tube axis' column
-    sum of phi (sampled every 10 steps).  Bounds are the measured errors with
-    a margin."""
+    sum of phi (sampled every 10 steps).
+
+    Measured: dL/dsigma agrees to 1.0e-3 (FP32) and 7.3e-3 (FP16 storage).
+    dL/dM and dL/dxi do not (FP32 1.10 and 0.61, FP16 storage 0.98 and 0.60
+    relative), and the FP64 rollout shows why: perturbing phi0 by 1e-7
+    relative (an FP32 rounding) moves its own dL/dM by 0.42 and dL/dxi by 0.44
+    while L moves by 1.3e-3 and dL/dsigma by 7e-4, so on this workload those
+    two gradients are ill-conditioned in any arithmetic below FP64 (the gas
+    circulates at up to ~0.1 with spurious currents that the phase-field
+    parameters feed).  The test bounds dL/dsigma by 2e-2 and each form's
+    dL/dM, dL/dxi error by 5x the FP64 rollout's own change under that
+    perturbation (measured: at most 2.6x)."""
     wl = W.config4(scale=2)
     N, K, x0 = wl.steps, 10, 32
     depth = _column_level(wl, x0)
@@ -271,12 +281,35 @@ def test_taylor_tube_reduced_precision_gradients_against_fp64():
     target = np.zeros(N // K)
     hi = _gpu_grads(wl, "fp64", "mrt", N, K, depth, target, x0=x0)
     say(f"  fp64: L {hi[0]:.6e} dM {hi[2]:.6e} dsigma {hi[3]:.6e} dxi {hi[5]:.6e}")
+    rng = np.random.default_rng(W.SEED + 2)
+    fluid = ~wl.solid
+    wl_p = dataclasses.replace(wl, phi0=np.where(fluid, wl.phi0 * (1 + 1e-7 * rng.standard_normal(
+        wl.phi0.shape)), 0.0))
+    e_cond = _grad_errors(_gpu_grads(wl_p, "fp64", "mrt", N, K, depth, target, x0=x0), hi)
+    say("  fp64 with phi0 perturbed by 1e-7: " + " ".join(f"{k} {v:.2e}" for k, v in e_cond.items()))
     e32 = _grad_errors(_gpu_grads(wl, "fp32", "mrt", N, K, depth, target, x0=x0), hi)
     say("  fp32 vs fp64: " + " ".join(f"{k} {v:.2e}" for k, v in e32.items()))
     e16 = _grad_errors(_gpu_grads(wl, "fp16s", "mrt", N, K, depth, target, x0=x0), hi)
     say("  fp16s vs fp64: " + " ".join(f"{k} {v:.2e}" for k, v in e16.items()))
     assert all(np.isfinite(v) for v in list(e32.values()) + list(e16.values()))
-    assert e32["dsigma"] <= 5e-2 and e16["dsigma"] <= 5e-2
+    assert e32["dsigma"] <= 2e-2 and e16["dsigma"] <= 2e-2
+    for k in ("dM", "dxi"):
+        assert e32[k] <= 5 * e_cond[k] and e16[k] <= 5 * e_cond[k], (k, e32[k], e16[k], e_cond[k])
+
+
+def test_fp32_adjoint_with_solids_tracks_fp64():
+    """FP32 forward and FP32 reverse step with solids (the masked kernels)
+    against FP64 on a small well-conditioned case (measured: dM 4.2e-6, dsigma
+    3.5e-6, dxi 2.1e-8, dphi0 2.6e-5 normwise; bound 2e-4)."""
+    wl = _small("mrt", True)
+    nsteps, K = 23, 1
+    target = np.random.default_rng(8).normal(0, 0.05, nsteps)
+    say("case: adjoint fp32 vs fp64 with solids")
+    hi = _gpu_grads(wl, "fp64", "mrt", nsteps, K, 12.0, target, ckpt=4)
+    lo = _gpu_grads(wl, "fp32", "mrt", nsteps, K, 12.0, target, ckpt=4)
+    e = _grad_errors(lo, hi)
+    say("  fp32 vs fp64: " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    assert e["dM"] <= 2e-4 and e["dsigma"] <= 2e-4 and e["dxi"] <= 2e-4 and e["dphi0"] <= 2e-4
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
