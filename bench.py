@@ -48,13 +48,13 @@ STEP_BYTES_D3Q27 = {"fp64": 880, "fp32": 440, "fp16s": 224}
 # same box (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE), keyed by form; taken for
 # the current kernel (profiles/k_step_hbm_traffic.txt) and re-measured
 # whenever it changes.  Forms without an entry report null.
-TRAFFIC = {"fp64_rising_bubble_128x512x128": 6.0528e9,
-           "fp32_rising_bubble_128x512x128": 3.4070e9,
-           "fp16s_rising_bubble_128x512x128": 1.5512e9,
-           "fp32_d3q27_phase_rising_bubble_128x512x128": 4.2509e9,
-           "fp32_drop_impact_384^3": 2.35292e10,
-           "fp16s_drop_impact_384^3": 1.11293e10,
-           "fp32_in_place_aa_rising_bubble_128x512x128": 3.0628e9}
+TRAFFIC = {"fp64_rising_bubble_128x512x128": 6.0850e9,
+           "fp32_rising_bubble_128x512x128": 3.4079e9,
+           "fp16s_rising_bubble_128x512x128": 1.5516e9,
+           "fp32_d3q27_phase_rising_bubble_128x512x128": 4.2830e9,
+           "fp32_drop_impact_384^3": 2.3531e10,
+           "fp16s_drop_impact_384^3": 1.1109e10,
+           "fp32_in_place_aa_rising_bubble_128x512x128": 3.0637e9}
 TRAFFIC_UNIT = "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
 DTYPE = {"fp32": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64"}
 
