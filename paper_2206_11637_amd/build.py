@@ -15,8 +15,7 @@ OUT = os.path.join(PKG, "libpflbm.so")
 # 27 h per cell, so its FP32 step runs 2 waves per SIMD instead of 3)
 VARIANTS = {
     "d3q15": (OUT, []),
-    "d3q27": (os.path.join(PKG, "libpflbm_d3q27.so"), ["-DPFLBM_PHASE_D3Q27", "-DPFLBM_F32_WAVES=2",
-                                                           "-DPFLBM_ADJ_WAVES=2"]),
+    "d3q27": (os.path.join(PKG, "libpflbm_d3q27.so"), ["-DPFLBM_PHASE_D3Q27", "-DPFLBM_F32_WAVES=2"]),
 }
 
 HIPCC_FLAGS = [

@@ -435,8 +435,13 @@ struct AdjArgs {
   Codec<R> cd;
 };
 
+// Occupancy request of the reverse cell kernel (FP32 arithmetic): 2 waves per
+// SIMD.  At 3 (168 VGPRs) it spilled 15-40 VGPRs to scratch; measured on the
+// 2000-step capillary rollout 64 x 128 x 64 (FP32) the reverse pass takes
+// 0.253 s at 2 waves against 0.277 s at 3, and the Taylor tube with FP16
+// storage is unchanged (3.77 s per 1000 steps).
 #ifndef PFLBM_ADJ_WAVES
-#define PFLBM_ADJ_WAVES 3
+#define PFLBM_ADJ_WAVES 2
 #endif
 template <typename S>
 struct AdjWaves { static constexpr int value = sizeof(S) == 8 ? 1 : PFLBM_ADJ_WAVES; };
