@@ -56,6 +56,17 @@ TRAFFIC = {"fp64_rising_bubble_128x512x128": 6.0850e9,
            "fp16s_drop_impact_384^3": 1.1109e10,
            "fp32_in_place_aa_rising_bubble_128x512x128": 3.0637e9}
 TRAFFIC_UNIT = "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
+# Vector ALU instructions per wave and z plane of the step kernel (= per cell
+# for one lane), rocprofv3 SQ_INSTS_VALU over SQ_WAVES and the planes each wave
+# marches (profiles/k_step_instruction_counts.txt), for the FP32-arithmetic
+# forms.  Their issue ceiling: a wave64 FP32 VALU instruction occupies a SIMD
+# for 4 cycles (16 lanes), so 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G wave
+# instructions per second (= 157.3 TFLOP/s FP32 vector / 64 lanes / 2 flops
+# per FMA / 2 for the packed forms, which these kernels do not use).
+VALU_PER_CELL = {"fp32_rising_bubble_128x512x128": 1197.3,
+                 "fp16s_rising_bubble_128x512x128": 1353.9,
+                 "fp16s_drop_impact_384^3": 1312.9}
+VALU_PEAK_G = 256 * 4 * 2.4 / 4
 DTYPE = {"fp32": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64"}
 
 
@@ -75,6 +86,20 @@ def roofline(name, bytes_per_cell, cells, kernel_ms, kernel):
             "traffic_over_algorithmic": None if tr is None else round(tr / alg, 4),
             "algorithmic_bytes_per_launch": alg, "bytes_per_cell": bytes_per_cell,
             "kernel": kernel, "kernel_ms": round(kernel_ms, 5)}
+
+
+def roofline_alu(name, cells, kernel_ms):
+    """Issue roofline of the step kernel for the forms whose instruction count
+    is committed: VALU wave instructions per launch over the kernel's average
+    duration against the FP32 VALU issue ceiling."""
+    n = VALU_PER_CELL.get(name)
+    if n is None:
+        return None
+    per_launch = n * cells / 64.0
+    achieved = per_launch / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "alu", "achieved": round(achieved, 1), "peak": VALU_PEAK_G,
+            "unit": "G VALU wave-instructions/s", "frac": round(achieved / VALU_PEAK_G, 4),
+            "valu_per_cell": n, "valu_per_launch": per_launch, "kernel_ms": round(kernel_ms, 5)}
 
 
 def time_form(name, wl, precision, steps, warmup, runs, collision="mrt", streaming="ab",
@@ -123,6 +148,7 @@ def time_form(name, wl, precision, steps, warmup, runs, collision="mrt", streami
                phi_kernel_ms=round(phi_avg, 5),
                effective_frac=round(mlups * sb / 1e3 / HBM_PEAK_GBPS, 4),
                roofline=roofline(name, kb, cells, cell_avg, kernel),
+               roofline_alu=roofline_alu(name, cells, cell_avg),
                mass=float(r[0]))
     del sim
     torch.cuda.empty_cache()

@@ -44,3 +44,27 @@ def test_reported_traffic_matches_the_committed_counter_summary():
     assert set(rows) == set(B.TRAFFIC)
     for name, total in rows.items():
         assert abs(B.TRAFFIC[name] - total) / total < 2e-3, (name, B.TRAFFIC[name], total)
+
+
+def test_reported_instruction_counts_match_the_committed_counter_summary():
+    """The issue roofline's VALU instructions per cell are those of the committed
+    rocprofv3 SQ counter summary (the current-kernel block), and its ceiling
+    follows from the unit counts: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles."""
+    sys.path.insert(0, ROOT)
+    import bench as B
+    path = os.path.join(ROOT, "profiles", "k_step_instruction_counts.txt")
+    rows = {}
+    cur = False
+    for line in open(path):
+        if line.startswith("kernel: "):
+            cur = True
+            continue
+        f = line.split()
+        if cur and len(f) > 3 and f[2] == "VALU":
+            rows[f"{f[0]}_{f[1]}"] = float(f[3])
+    for name, n in B.VALU_PER_CELL.items():
+        assert rows[name] == n, (name, rows.get(name), n)
+    assert abs(B.VALU_PEAK_G - 614.4) < 1e-9
+    r = B.roofline_alu("fp16s_drop_impact_384^3", 56623104, 3.0)
+    assert r["bound"] == "alu" and abs(r["achieved"] - 1312.9 * 56623104 / 64 / 3e-3 / 1e9) < 0.1
+    assert B.roofline_alu("fp64_rising_bubble_128x512x128", 8388608, 1.0) is None
