@@ -62,6 +62,9 @@ RAGGED = [
     # several tiles in x and y, interior ones included
     (200, 20, 12, (True, False, True), 0.0, 5),
     (200, 20, 12, (False, False, False), 0.0, 5),
+    # walls in x only: every wave takes the FP64 kernel's x-wall fast path,
+    # the ragged last tile (130 = 2 x 64 + 2) included
+    (130, 12, 10, (False, True, True), 0.0, 6),
 ]
 
 
