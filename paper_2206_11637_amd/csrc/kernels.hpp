@@ -821,7 +821,8 @@ struct CellArgs {
 // AA cache policy (measured on the rising-bubble lattice, FP32): even steps
 // (own slots, aligned rows) stream with non-temporal loads and stores; odd
 // steps (neighbour slots, rows one element off alignment, lines shared by
-// neighbouring waves) use cached loads and non-temporal stores.
+// neighbouring waves) use cached loads and non-temporal stores (non-temporal
+// odd loads: AA step -10 %; cached odd stores: no change).
 template <bool ODD> struct AaPolicy {
   static constexpr bool nt_load = !ODD;
   static constexpr bool nt_store = true;
@@ -949,7 +950,12 @@ __global__ __launch_bounds__(256) void k_light(LightArgs<S> a) {
       const Nbhd nb = make_nbhd(x, y, z, G);
       const R ref = phi_ref_of<S>(a.phi_prev, idx);
       R h[Q_H], g[Q_G];
-      load_h<S, RULE, false>(a.h, G.N, idx, nb, walls, a.cd.inv_scale_h, h);
+      // the gather of a state read with the even AA rule (own slots, aligned
+      // rows) streams its rows non-temporally: measured on the rising-bubble
+      // lattice (FP32) 0.114 ms against 0.170 ms cached, the AA step 2.3 %
+      // faster; the odd rule's shifted rows keep cached loads
+      load_h<S, RULE, RULE == RULE_AA_EVEN && LM == LM_GATHER>(a.h, G.N, idx, nb, walls,
+                                                              a.cd.inv_scale_h, h);
       if (LM == LM_GATHER) {
         a.phi_out[idx] = phi_of(h, ref);
       } else {
