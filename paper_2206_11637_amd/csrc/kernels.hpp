@@ -510,6 +510,32 @@ __device__ __forceinline__ void load_g(const S* __restrict__ Gp, long long N, un
   }
 }
 
+// The same pulls of g with the stored values kept as they are, each in a
+// register of its own (an FP16 value zero-extended, so no load writes half a
+// register), and decoded where they are used, so that the loads stay in
+// flight until then.
+template <typename S> struct Raw { using T = S; };
+template <> struct Raw<_Float16> { using T = unsigned; };
+template <typename S, int RULE, bool NT>
+__device__ __forceinline__ void load_g_raw(const S* __restrict__ Gp, long long N, unsigned idx,
+                                           const Nbhd& nb, unsigned walls,
+                                           typename Raw<S>::T (&g)[Q_G]) {
+  const unsigned NS = (unsigned)(N * (long long)sizeof(S));
+#pragma unroll
+  for (int i = 0; i < Q_G; ++i) {
+    const char* p = pair_base(Gp, N, i) + read_off<S, true, RULE>(i, idx, nb, walls, NS);
+    if constexpr (sizeof(S) == 2) g[i] = ld_nt<NT>(reinterpret_cast<const unsigned short*>(p));
+    else g[i] = ld_nt<NT>(reinterpret_cast<const S*>(p));
+  }
+}
+template <typename S>
+__device__ __forceinline__ typename Store<S>::R decode_raw(typename Raw<S>::T v,
+                                                          typename Store<S>::R inv_scale) {
+  if constexpr (sizeof(S) == 2)
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(v))) * inv_scale;
+  else return v;
+}
+
 // phi^{n-1}(self), the reference of the shifted forms (0 in FP64)
 template <typename S>
 __device__ __forceinline__ typename Store<S>::R phi_ref_of(const typename Store<S>::R* __restrict__ phi_prev,
@@ -797,6 +823,234 @@ void k_step(StepArgs<S> a) {
       const Planes<R> pl{pm, p0, pp, TX, lx, ly};
       store_own<S, kNtStore>(a.h_out, a.g_out, G.N, idx, a.cd, ref, phi, pl, h, g);
     }
+  }
+}
+
+// ---- pipelined step: h pulls straight into LDS, two planes ahead ------------
+// The FP32 form of the D3Q15 build issues the h pulls of plane z + 2 as
+// global-to-LDS loads (one dword per lane) while plane z collides, and the g
+// pulls of plane z + 1 once plane z's g has been stored, so that neither
+// waits in registers nor exposes its latency at the next plane's phase-field
+// sum.  Same arithmetic in the same order as k_step (bitwise the same
+// results); the own cells' raw h wait in LDS until their collision, the ring
+// cells' raw h until their phi.  Measured against k_step on one GPU: FP32
+// drop impact 384^3 4.34 against 4.51 ms, rising bubble equal (0.635 /
+// 0.632 ms).  The kernel is written for FP16 storage too (an FP16 value lands
+// in the low half of its dword; tested bitwise against the in-place scheme),
+// but there it needs 168 VGPRs with scratch spills at 3 waves per SIMD (5.26
+// against 3.21 ms on the drop) and is 3-6 % slower at 2, so FP16 storage
+// keeps k_step.  The D3Q27 phase lattice's 27 h per cell do not fit the LDS.
+template <typename S>
+struct DmaStep { static constexpr bool value = sizeof(S) == 4 && Q_H == 15; };
+constexpr int kRingMax = 140;   // ring cells of the 64 x 4 tile, the largest of the tile shapes
+
+template <typename R>
+struct PlaneState {
+  unsigned walls;   // own cell's wall bits (box faces and solid neighbours)
+  bool skip;        // own position outside the lattice or solid
+  R ref;            // own cell's shift reference phi^{n-1}
+  bool hskip;       // ring cell outside the lattice or solid (or no ring cell)
+  R href;           // ring cell's shift reference
+};
+
+// every LDS read issued so far has returned (lgkmcnt 0), and the compiler
+// moves no memory access across this point
+__device__ __forceinline__ void lds_settled() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// one element per lane from global memory straight into LDS: lane l's value
+// lands in the dword at lds_wave + l (an FP16 value in its low half); the
+// size is written as a literal (a template-dependent size crashes this
+// compiler's instruction selection)
+template <typename S>
+__device__ __forceinline__ void dma_pull(const S* gp, unsigned* lds_wave) {
+  auto* l = (__attribute__((address_space(3))) void*)lds_wave;
+  if constexpr (sizeof(S) == 2) __builtin_amdgcn_global_load_lds(gp, l, 2, 0, 0);
+  else __builtin_amdgcn_global_load_lds(gp, l, 4, 0, 0);
+}
+
+template <typename S, bool MRT, bool MASK, bool GUO>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<S>::value)))
+void k_step_dma(StepArgs<S> a) {
+  using St = Store<S>;
+  using R = typename St::R;
+  static_assert(sizeof(S) != 8 && Q_H == 15, "pipelined step: FP32 arithmetic, D3Q15 phase field");
+  constexpr int E = 4 / (int)sizeof(S);      // S elements per LDS dword
+  __shared__ unsigned own_raw[2][Q_H][256];
+  __shared__ unsigned ring_raw[2][Q_H][kRingMax];
+  extern __shared__ unsigned char smem_raw[];
+  const Geom& G = a.geo;
+  const int TX = G.bx + 2, TY = G.by + 2, TXY = TX * TY;
+  R* ring = reinterpret_cast<R*>(smem_raw);     // [4][TY][TX]
+  const ChunkCoord t = chunk_of_block(G);
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + ly * G.bx;
+  const unsigned wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
+  const int x = t.x0 + lx, y = t.y0 + ly;
+  const bool active = x < G.nx && y < G.ny;
+  int ox = x, oy = y;
+  const bool own_ok = wrap(ox, G.nx, G.px) && wrap(oy, G.ny, G.py);
+  const int opos = (ly + 1) * TX + lx + 1;
+  // ring cells beyond the LDS slots (no tile shape has them) are not pulled
+  const int NH = min(2 * TX + 2 * G.by, kRingMax);
+  int hpos = 0, hx = 0, hy = 0;
+  bool halo_ok = false;
+  if (tid < NH) {
+    int ix, iy;
+    if (tid < TX) { ix = tid; iy = 0; }
+    else if (tid < 2 * TX) { ix = tid - TX; iy = TY - 1; }
+    else if (tid < 2 * TX + G.by) { ix = 0; iy = 1 + tid - 2 * TX; }
+    else { ix = TX - 1; iy = 1 + tid - 2 * TX - G.by; }
+    hpos = iy * TX + ix;
+    hx = t.x0 - 1 + ix;
+    hy = t.y0 - 1 + iy;
+    halo_ok = wrap(hx, G.nx, G.px) && wrap(hy, G.ny, G.py);
+  }
+  const unsigned sxy = (unsigned)G.nx * (unsigned)G.ny;
+  const unsigned NS = (unsigned)(G.N * (long long)sizeof(S));
+
+  // pulls of plane p into the LDS slots of its parity; the plane's wall bits,
+  // skip flags and shift references into ps
+  auto issue = [&](int p, PlaneState<R>& ps) {
+    int pz = p;
+    const bool zok = wrap(pz, G.nz, G.pz);
+    ps.skip = true;
+    ps.hskip = true;
+    ps.walls = 0;
+    ps.ref = R(0);
+    ps.href = R(0);
+    {
+      const unsigned idx = ox + G.nx * oy + sxy * pz;
+      bool sol = true;
+      if (own_ok && zok) ps.walls = cell_walls<MASK>(ox, oy, pz, idx, G, a.nbr, sol);
+      if (own_ok && zok && !sol) {
+        ps.skip = false;
+        ps.ref = phi_ref_of<S>(a.phi_prev, idx);
+        const Nbhd nb = make_nbhd(ox, oy, pz, G);
+#pragma unroll
+        for (int i = 0; i < Q_H; ++i)
+          dma_pull(reinterpret_cast<const S*>(pair_base(a.h_in, G.N, i) +
+                                              read_off<S, false, RULE_AB>(i, idx, nb, ps.walls, NS)),
+                   &own_raw[p & 1][i][wave0]);
+      }
+    }
+    if (tid < NH) {
+      const unsigned idx = hx + G.nx * hy + sxy * pz;
+      bool sol = true;
+      unsigned w = 0;
+      if (halo_ok && zok) w = cell_walls<MASK>(hx, hy, pz, idx, G, a.nbr, sol);
+      if (halo_ok && zok && !sol) {
+        ps.hskip = false;
+        ps.href = phi_ref_of<S>(a.phi_prev, idx);
+        const Nbhd nb = make_nbhd(hx, hy, pz, G);
+#pragma unroll
+        for (int i = 0; i < Q_H; ++i)
+          dma_pull(reinterpret_cast<const S*>(pair_base(a.h_in, G.N, i) +
+                                              read_off<S, false, RULE_AB>(i, idx, nb, w, NS)),
+                   &ring_raw[p & 1][i][wave0]);
+      }
+    }
+  };
+  // raw h of this thread's own cell (plane parity s), decoded
+  auto own_h = [&](int s, R (&h)[Q_H]) {
+#pragma unroll
+    for (int i = 0; i < Q_H; ++i)
+      h[i] = St::template ld<false>(reinterpret_cast<const S*>(&own_raw[s][i][0]) + E * tid,
+                                    a.cd.inv_scale_h);
+  };
+  // phi^n of plane p into the ring (sentinel for walls and solids)
+  auto phi_plane = [&](int p, const PlaneState<R>& ps) {
+    R* rp = ring + (p & 3) * TXY;
+    R v = sentinel<R>();
+    if (!ps.skip) {
+      R hh[Q_H];
+      own_h(p & 1, hh);
+      v = phi_of(hh, ps.ref);
+    }
+    rp[opos] = v;
+    if (tid < NH) {
+      R hv = sentinel<R>();
+      if (!ps.hskip) {
+        R hh[Q_H];
+#pragma unroll
+        for (int i = 0; i < Q_H; ++i)
+          hh[i] = St::template ld<false>(reinterpret_cast<const S*>(&ring_raw[p & 1][i][0]) + E * tid,
+                                         a.cd.inv_scale_h);
+        hv = phi_of(hh, ps.href);
+      }
+      rp[hpos] = hv;
+    }
+  };
+
+  PlaneState<R> s0, s1, s2;
+  issue(t.z0 - 1, s0);
+  issue(t.z0, s1);
+  phi_plane(t.z0 - 1, s0);
+  lds_settled();
+  issue(t.z0 + 1, s2);         // into the slots of plane z0 - 1, consumed above
+  phi_plane(t.z0, s1);
+  s0 = s1;
+  s1 = s2;
+  typename Raw<S>::T graw[Q_G];
+  {
+    const unsigned idx = x + G.nx * y + sxy * t.z0;
+    if (active && !s0.skip)
+      load_g_raw<S, RULE_AB, kNtGPull>(a.g_in, G.N, idx, make_nbhd(x, y, t.z0, G), s0.walls, graw);
+  }
+  for (int z = t.z0; z < t.z1; ++z) {
+    // s0: plane z (phi in the ring, raw h in LDS, raw g in registers);
+    // s1: plane z + 1 (pulls in flight)
+    phi_plane(z + 1, s1);
+    __syncthreads();
+    const bool work = active && !s0.skip;
+    const unsigned idx = x + G.nx * y + sxy * z;
+    R h[Q_H];
+    if (work) own_h(z & 1, h);
+    // the slot's values are in registers before its refill is issued
+    lds_settled();
+    const R* pm = ring + ((z - 1) & 3) * TXY;
+    const R* p0 = ring + (z & 3) * TXY;
+    const R* pp = ring + ((z + 1) & 3) * TXY;
+    const R phi = p0[opos];
+    CellState<R> c;
+    if (work) {
+      R g[Q_G];
+#pragma unroll
+      for (int i = 0; i < Q_G; ++i) g[i] = decode_raw<S>(graw[i], a.cd.inv_scale_g);
+      R Gx, Gy, Gz, lap;
+      stencil3(pm, p0, pp, TX, lx, ly, Gx, Gy, Gz, lap);
+      prologue(phi, sum_h(h), g, Gx, Gy, Gz, lap, a.P, c);
+      collide_g<R, MRT, GUO>(g, c, a.P);
+      // the stores walk the population rows (one address add each); g first
+      // so that its registers take the next plane's pulls
+      S* p = next_row(a.g_out, (long long)idx);
+#pragma unroll
+      for (int i = 0; i < Q_G; ++i) {
+        St::template st<kNtStore>(p, g[i], a.cd.scale_g);
+        if (i + 1 < Q_G) p = next_row(p, G.N);
+      }
+    }
+    // g of plane z + 1, then the h of plane z + 2 into the slots plane z has
+    // left: in flight over the h collision and stores of this plane and the
+    // next plane's phase-field sum, with only the h stores issued after them
+    if (z + 1 < t.z1 && active && !s1.skip)
+      load_g_raw<S, RULE_AB, kNtGPull>(a.g_in, G.N, idx + sxy, make_nbhd(x, y, z + 1, G), s1.walls,
+                                       graw);
+    if (z + 2 <= t.z1) issue(z + 2, s2);
+    if (work) {
+      collide_h<R, MRT>(h, c, a.P);
+      if (St::kShift) a.phi_out[idx] = phi;
+      if (a.phi_src_out) a.phi_src_out[idx] = phi;
+      const Planes<R> pl{pm, p0, pp, TX, lx, ly};
+      S* p = next_row(a.h_out, (long long)idx);
+#pragma unroll
+      for (int i = 0; i < Q_H; ++i) {
+        St::template st<kNtStore>(p, rebase<S>(i, h[i], s0.ref, phi, pl), a.cd.scale_h);
+        if (i + 1 < Q_H) p = next_row(p, G.N);
+      }
+    }
+    s0 = s1;
+    s1 = s2;
   }
 }
 

@@ -41,6 +41,11 @@ size_t real_size(int precision) { return precision == PFLBM_FP64 ? 8 : 4; }
 static_assert(PFLBM_TILE_X >= 16 && PFLBM_TILE_X <= 64 && 256 % PFLBM_TILE_X == 0 &&
                   2 * (PFLBM_TILE_X + 2) + 2 * (256 / PFLBM_TILE_X) <= 256,
               "unsupported tile width");
+// the pipelined step keeps the raw h of at most kRingMax ring cells in LDS;
+// every tile the host picks (bx = PFLBM_TILE_X, 32 or 16) stays within it
+static_assert(2 * (PFLBM_TILE_X + 2) + 2 * (256 / PFLBM_TILE_X) <= kRingMax &&
+                  2 * (32 + 2) + 2 * 8 <= kRingMax && 2 * (16 + 2) + 2 * 16 <= kRingMax,
+              "ring larger than the pipelined step's LDS slots");
 #ifndef PFLBM_STEP_BLOCKS
 #define PFLBM_STEP_BLOCKS 2048
 #endif
@@ -280,15 +285,22 @@ StepArgs<S> step_args(pflbm_ctx* c) {
 
 template <typename S, bool MRT, bool GUO>
 void launch_step_k(pflbm_ctx* c, const StepArgs<S>& a, dim3 grd, dim3 blk, size_t sm) {
-  if (c->d.has_mask) hipLaunchKernelGGL((k_step<S, MRT, true, GUO>), grd, blk, sm, c->stream, a);
-  else hipLaunchKernelGGL((k_step<S, MRT, false, GUO>), grd, blk, sm, c->stream, a);
+  if constexpr (DmaStep<S>::value) {
+    if (c->d.has_mask) hipLaunchKernelGGL((k_step_dma<S, MRT, true, GUO>), grd, blk, sm, c->stream, a);
+    else hipLaunchKernelGGL((k_step_dma<S, MRT, false, GUO>), grd, blk, sm, c->stream, a);
+  } else {
+    if (c->d.has_mask) hipLaunchKernelGGL((k_step<S, MRT, true, GUO>), grd, blk, sm, c->stream, a);
+    else hipLaunchKernelGGL((k_step<S, MRT, false, GUO>), grd, blk, sm, c->stream, a);
+  }
 }
 
 template <typename S>
 void launch_step(pflbm_ctx* c, const StepArgs<S>& a) {
   using R = typename Store<S>::R;
-  // 4-plane phi ring + two planes of the threads' own h
-  const size_t sm = ((size_t)4 * (c->L.bx + 2) * (c->L.by + 2) + 2 * Q_H * 256) * sizeof(R);
+  // 4-plane phi ring, + two planes of the threads' own h where the kernel
+  // keeps them in dynamic LDS (the pipelined kernel's raw slots are static)
+  const size_t ring = (size_t)4 * (c->L.bx + 2) * (c->L.by + 2);
+  const size_t sm = (ring + (DmaStep<S>::value ? 0 : 2 * Q_H * 256)) * sizeof(R);
   const dim3 blk(c->L.bx, c->L.by), grd(c->L.nblocks_step);
   const bool mrt = c->d.collision == PFLBM_MRT, guo = c->d.forcing == PFLBM_FORCING_GUO;
   if (mrt) {
