@@ -28,7 +28,9 @@
 // grad/lap stencils read three ring planes.  Pulling the ring cells' h re-reads data that the
 // neighbouring tiles read too (mostly from L2).  This needs the second
 // buffer: in place, a neighbouring block could overwrite a ring cell's
-// populations before they are summed.
+// populations before they are summed.  The FP32 form runs k_step_dma, the
+// same step with the h pulls of plane z + 2 sent straight into LDS while
+// plane z collides.
 //
 // In-place AA pattern (one buffer per lattice, half the population memory):
 //   even step: read own slots f[i][x], write f*_i into own slot f[opp i][x];
