@@ -439,7 +439,8 @@ def main():
     ap.add_argument("--runs", type=int, default=5, help="timed runs; the median run is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--only", default="", help="comma-separated form names (no slow legs)")
+    ap.add_argument("--only", default="",
+                    help="comma-separated form names (of the slow legs only the adjoint_ ones)")
     ap.add_argument("--precision", default="fp64", choices=["fp32", "fp16s", "fp64"],
                     help="storage/arithmetic form of the headline run (default fp64, the paper's)")
     ap.add_argument("--adj-steps", type=int, default=4000,
@@ -532,6 +533,8 @@ def main():
             form("precision_errors_drop_impact_384^3_M0.03", precision_errors, wl2s,
                  (100, 500, 1000, 5000))
             del wl2s
+        # the reverse-mode legs also run when --only names them
+        if slow or any(n.startswith("adjoint_") for n in only):
             wl3 = W.config3()
             form("adjoint_capillary_64x128x64_fp32", adjoint_form, wl3, "fp32", wl3.steps, 10, 0,
                  64.0)
