@@ -73,11 +73,11 @@ __device__ __forceinline__ R second_moment_t(Dir d, const Sym<R>& L) {
 // xi/2, so dtheta/dxi = -theta/xi and dmu/dxi = -(4 beta p3c + kappa lap)/xi
 // with p3c = phi (phi - 1)(phi - 1/2)).  BULK: the
 // bulk mode of g relaxes at P.s_bulk (MRT only); GUO: Guo's full source.
-template <typename R, bool MRT, bool BULK, bool GUO>
+template <typename R, bool MRT, bool BULK, bool GUO, typename LoadL>
 __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R Gx, R Gy, R Gz,
                                          R lap, const Phys<R>& P, const AdjConst<R>& K,
-                                         R (&lh)[Q_H], R (&lg)[Q_G], R& lGx, R& lGy, R& lGz,
-                                         R& lL, R& l_omphi, R& l_sigma, R& l_xi) {
+                                         R (&lh)[Q_H], R (&lg)[Q_G], LoadL&& load_l, R& lGx, R& lGy,
+                                         R& lGz, R& lL, R& l_omphi, R& l_sigma, R& l_xi) {
   // ---------------- forward recomputation ----------------
   const R phi = sum_h(h);
   const R rho = P.rho_L + phi * P.drho;
@@ -123,6 +123,7 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   const R uu = ux * ux + uy * uy + uz * uz;
 
   // ---------------- phase-field collision, reverse ----------------
+  load_l(lh, 0);
   const R omp = P.omega_phi;
   const R fkh = (R(1) - R(0.5) * omp) * theta;
   const R sh = MRT ? P.s_high : omp;
@@ -213,6 +214,7 @@ __device__ __forceinline__ void cell_vjp(const R (&h)[Q_H], const R (&g)[Q_G], R
   R l_uu = -R(1.5) * l_hbase;
 
   // ---------------- hydrodynamic collision, reverse ----------------
+  load_l(lg, 1);
   const R fk = (R(1) - R(0.5) * om) * R(3) / rho;
   const R base = p - R(1.5) * uu;
   const R s = MRT ? P.s_high : om;
@@ -436,15 +438,21 @@ struct AdjArgs {
 };
 
 // Occupancy request of the reverse cell kernel (FP32 arithmetic): 2 waves per
-// SIMD.  At 3 (168 VGPRs) it spilled 15-40 VGPRs to scratch; measured on the
-// 2000-step capillary rollout 64 x 128 x 64 (FP32) the reverse pass takes
-// 0.253 s at 2 waves against 0.277 s at 3, and the Taylor tube with FP16
-// storage is unchanged (3.77 s per 1000 steps).
+// SIMD with FP32 storage, 3 with FP16 storage.  With the Lambda loads issued
+// where they are first needed, the FP16-storage MRT kernels fit 168 VGPRs
+// (the masked one, the Taylor tube's, without a spill); the FP32 ones need
+// 169 and spilled 15-40 VGPRs at 3 waves before that change (capillary
+// rollout 64 x 128 x 64: 0.253 s at 2 waves against 0.277 s at 3).
 #ifndef PFLBM_ADJ_WAVES
 #define PFLBM_ADJ_WAVES 2
 #endif
+#ifndef PFLBM_ADJ_F16_WAVES
+#define PFLBM_ADJ_F16_WAVES 3
+#endif
 template <typename S>
-struct AdjWaves { static constexpr int value = sizeof(S) == 8 ? 1 : PFLBM_ADJ_WAVES; };
+struct AdjWaves {
+  static constexpr int value = sizeof(S) == 8 ? 1 : (sizeof(S) == 2 ? PFLBM_ADJ_F16_WAVES : PFLBM_ADJ_WAVES);
+};
 
 template <typename S, bool MRT, int RULE, bool MASK, bool BULK, bool GUO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjWaves<S>::value)))
@@ -480,27 +488,35 @@ void k_adj_cell(AdjArgs<S> a) {
     // transposed streaming: Lambda of the slot each post-collision value went to
     R lh[Q_H], lg[Q_G];
     const unsigned NS = (unsigned)(G.N * (long long)sizeof(R));
+    // the Lambda loads are issued where the reverse step first needs them
+    // (lh before the phase-field part, lg before the hydrodynamic part), so
+    // neither array is held in registers through the other part
+    auto load_l = [&](auto& l, int which) {
+      if (which == 0) {
 #pragma unroll
-    for (int i = 0; i < Q_H; ++i) {
-      const Dir d = ch(i);
-      unsigned cell = idx;
-      unsigned off = pair_off<R>(opp(i), idx, NS);
-      if (i && !(walls & (1u << nb27(d.x, d.y, d.z)))) {
-        cell = nb.at(d.x, d.y, d.z);
-        off = pair_off<R>(i, cell, NS);
+        for (int i = 0; i < Q_H; ++i) {
+          const Dir d = ch(i);
+          unsigned cell = idx;
+          unsigned off = pair_off<R>(opp(i), idx, NS);
+          if (i && !(walls & (1u << nb27(d.x, d.y, d.z)))) {
+            cell = nb.at(d.x, d.y, d.z);
+            off = pair_off<R>(i, cell, NS);
+          }
+          l[i] = *reinterpret_cast<const R*>(pair_base(a.lh_in, G.N, i) + off) + a.aphi_in[cell];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q_G; ++i) {
+          const Dir d = cg(i);
+          unsigned off = pair_off<R>(opp(i), idx, NS);
+          if (i && !(walls & (1u << nb27(d.x, d.y, d.z)))) off = pair_off<R>(i, nb.at(d.x, d.y, d.z), NS);
+          l[i] = *reinterpret_cast<const R*>(pair_base(a.lg_in, G.N, i) + off);
+        }
       }
-      lh[i] = *reinterpret_cast<const R*>(pair_base(a.lh_in, G.N, i) + off) + a.aphi_in[cell];
-    }
-#pragma unroll
-    for (int i = 0; i < Q_G; ++i) {
-      const Dir d = cg(i);
-      unsigned off = pair_off<R>(opp(i), idx, NS);
-      if (i && !(walls & (1u << nb27(d.x, d.y, d.z)))) off = pair_off<R>(i, nb.at(d.x, d.y, d.z), NS);
-      lg[i] = *reinterpret_cast<const R*>(pair_base(a.lg_in, G.N, i) + off);
-    }
+    };
     R lGx, lGy, lGz, lL, lomp, lsig, lxi;
-    cell_vjp<R, MRT, BULK, GUO>(h, g, Gx, Gy, Gz, lap, a.P, a.K, lh, lg, lGx, lGy, lGz, lL, lomp, lsig,
-                                lxi);
+    cell_vjp<R, MRT, BULK, GUO>(h, g, Gx, Gy, Gz, lap, a.P, a.K, lh, lg, load_l, lGx, lGy, lGz, lL,
+                                lomp, lsig, lxi);
 #pragma unroll
     for (int i = 0; i < Q_H; ++i) *slot(a.lh_out, G.N, i, idx) = lh[i];
 #pragma unroll
