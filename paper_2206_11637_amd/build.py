@@ -12,12 +12,12 @@ ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "pflbm.hip")
 OUT = os.path.join(PKG, "libpflbm.so")
 # build variants: output file and extra flags (the D3Q27 phase lattice holds
-# 27 h per cell, so its FP32 step and its FP16-storage reverse step run 2
-# waves per SIMD instead of 3)
+# 27 h per cell, so its FP32-arithmetic step and reverse step run 2 waves per
+# SIMD instead of 3)
 VARIANTS = {
     "d3q15": (OUT, []),
     "d3q27": (os.path.join(PKG, "libpflbm_d3q27.so"), ["-DPFLBM_PHASE_D3Q27", "-DPFLBM_F32_WAVES=2",
-                                                           "-DPFLBM_ADJ_F16_WAVES=2"]),
+                                                           "-DPFLBM_ADJ_WAVES=2"]),
 }
 
 HIPCC_FLAGS = [

@@ -437,17 +437,19 @@ struct AdjArgs {
   Codec<R> cd;
 };
 
-// Occupancy request of the reverse cell kernel (FP32 arithmetic): 2 waves per
-// SIMD with FP32 storage, 3 with FP16 storage.  With the Lambda loads issued
-// where they are first needed, the FP16-storage MRT kernels fit 168 VGPRs
-// (the masked one, the Taylor tube's, without a spill); the FP32 ones need
-// 169 and spilled 15-40 VGPRs at 3 waves before that change (capillary
-// rollout 64 x 128 x 64: 0.253 s at 2 waves against 0.277 s at 3).
+// Occupancy request of the reverse cell kernel (FP32 arithmetic): 3 waves
+// per SIMD.  With the Lambda loads issued where they are first needed, the
+// FP16-storage MRT kernels fit its 168 VGPRs (the masked one, the Taylor
+// tube's, without a spill) and the FP32 ones spill about 4; measured: the
+// tube's reverse pass 3.41 s per 1000 steps against 3.75 s at 2 waves with
+// the earlier load order, the 2000-step capillary rollout 64 x 128 x 64 in
+// FP32 0.239 s against 0.252 s at 2 waves.  Before the load order changed, 3
+// waves spilled 15-40 VGPRs and lost (0.277 s on the capillary rollout).
 #ifndef PFLBM_ADJ_WAVES
-#define PFLBM_ADJ_WAVES 2
+#define PFLBM_ADJ_WAVES 3
 #endif
 #ifndef PFLBM_ADJ_F16_WAVES
-#define PFLBM_ADJ_F16_WAVES 3
+#define PFLBM_ADJ_F16_WAVES PFLBM_ADJ_WAVES
 #endif
 template <typename S>
 struct AdjWaves {
