@@ -1,6 +1,8 @@
 """Standing gravity and capillary waves through the library against their
 closed forms (paper sec. "Standing waves"; setup and readings in
-tests/wave_study.py), short version: L = 50 and 100 up to t* = 20.
+tests/wave_study.py), short version: L = 50 and 100 up to t* = 20 on the
+default build, and L = 100 and 200 up to t* = 40 on the paper's D2Q9 pair
+(planar lattices of the D3Q27-phase build).
 
 What is pinned: the wave converges towards the analytic amplitude as L grows
 (RMS error of a*(t*) and first-minimum time), the phase mass is conserved to
@@ -46,3 +48,27 @@ def test_fp32_and_fp64_waves_agree():
     say(f"  gravity L=50 to t*=20: max |a*(fp32) - a*(fp64)| = {d:.2e}; "
         f"mass drift fp32 {r32['mass_drift']:.1e} fp64 {r64['mass_drift']:.1e}")
     assert d < 2e-3
+
+
+@pytest.mark.parametrize("kind", ["gravity", "capillary"])
+def test_d2q9_pair_converges_from_l100_to_l200(kind):
+    """The paper's D2Q9 pair (planar lattices of the D3Q27-phase build) from
+    L = 100 to L = 200 over t* = 40: the first minimum moves towards the
+    closed form's and the rms error of a*(t*) falls (the full study to t* = 80
+    at L = 50 to 400: tests/results/standing_waves_d2q9.md, first-minimum time
+    errors 5.3 % -> 4.7 % (gravity) and 3.4 % -> 2.6 % (capillary) from L = 100
+    to 200); phase mass to rounding over ~2 x 10^6 FP32 steps."""
+    import wave_study as S
+    runs = {}
+    for L in (100, 200):
+        r = S.run(kind, L, 40.0, "fp32", phase="d3q27")
+        runs[L] = r
+        say(f"  {kind} D2Q9 L={L}: rms {r['rms']:.4f} first minimum t* {r['t_min']:.3f} "
+            f"(ref {r['t_min_ref']:.3f}) a* {r['a_min']:.4f} (ref {r['a_min_ref']:.4f}) "
+            f"mass drift {r['mass_drift']:.1e} [{r['steps']} steps]")
+        assert abs(r["mass_drift"]) < 1e-7
+    e100 = abs(runs[100]["t_min"] / runs[100]["t_min_ref"] - 1)
+    e200 = abs(runs[200]["t_min"] / runs[200]["t_min_ref"] - 1)
+    assert e200 < e100 and e200 < 0.06
+    assert runs[200]["rms"] < runs[100]["rms"]
+    assert abs(runs[200]["a_min"] / runs[200]["a_min_ref"] - 1) < 0.05
