@@ -233,6 +233,9 @@ def run(D: int, precision: str = "fp64", gauge: str = "mid", streaming: str = "a
     elif ts and ts[-1] > 10.0 and 10.0 in tv:
         U = (ys[-1] - tv[10.0]) / ((ts[-1] - 10.0) * c.t_ref)
         out["Re_last"] = float(c.D) * U / c.mu_H
+        ta = {round(t, 6): y for t, y in zip(ts, ys_all)}
+        U_all = (ys_all[-1] - ta[10.0]) / ((ts[-1] - 10.0) * c.t_ref)
+        out["Re_last_all_cells"] = float(c.D) * U_all / c.mu_H
         out["Re_last_window"] = (10.0, ts[-1])
     del sim
     torch.cuda.empty_cache()
@@ -370,6 +373,34 @@ def diagnose(D: int, precision: str = "fp32", tmax: float = 15.0, every: float =
     return out
 
 
+def write_table(res, path, argv):
+    """Results table (markdown) of the runs in res."""
+    rows = ["| D | lattice | precision | phase lattice | steps | Re, gas region | Re, all cells | "
+            "window t* | paper PFLBM | phase-mass drift | GPU s |",
+            "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for r in res:
+        D = r["D"]
+        lat = f"{D}x{10 * D}x{D}"
+        if "Re" in r:
+            re_gas, re_all, win = f"{r['Re']:.3f}", f"{r['Re_all_cells']:.3f}", "10-15"
+        elif "Re_last" in r:
+            re_gas, re_all = f"{r['Re_last']:.3f}", f"{r.get('Re_last_all_cells', float('nan')):.3f}"
+            win = f"10-{r['Re_last_window'][1]:g} (non-finite before 15)"
+        else:
+            re_gas, re_all, win = "diverges", "", ""
+        drift = r.get("mass_drift")
+        drift = f"{drift:.1e}" if isinstance(drift, float) else "-"
+        rows.append(f"| {D} | {lat} | {r['precision']} | {r.get('phase_lattice', 'd3q15')} | {r['steps']} | "
+                    f"{re_gas} | {re_all} | {win} | {r['re_paper'] or '-'} | {drift} | {r['seconds']:.0f} |")
+    head = ("# The paper's Taylor bubble on the GPU: Reynolds number of the rise\n\n"
+            "Written by `python tests/taylor_study.py " + argv + "` on one MI355X (MRT with the bulk\n"
+            "rate s_bulk = 1, two buffers; Re = rho_H D U / mu_H with U the rise velocity of the centre of\n"
+            "mass over the window; gas region: weights 1 - phi over cells with phi < 1/2; all cells: over\n"
+            "every fluid cell).\n\n")
+    with open(path, "w") as f:
+        f.write(head + "\n".join(rows) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--D", type=int, nargs="+", default=[64, 128])
@@ -380,6 +411,7 @@ def main():
     ap.add_argument("--every", type=float, default=0.5)
     ap.add_argument("--phase-lattice", default="d3q15", choices=["d3q15", "d3q27"])
     ap.add_argument("--out", default=None)
+    ap.add_argument("--table", default=None, help="write a markdown table of the runs here")
     ap.add_argument("--diagnose", action="store_true",
                     help="per-sample diagnostics and the first non-finite step (first --D, --precision)")
     args = ap.parse_args()
@@ -415,6 +447,8 @@ def main():
                 if args.out:
                     with open(args.out, "w") as f:
                         json.dump(res, f)
+                if args.table:
+                    write_table(res, args.table, " ".join(sys.argv[1:]))
 
 
 if __name__ == "__main__":
