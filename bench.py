@@ -158,8 +158,9 @@ def time_form(name, wl, precision, steps, warmup, runs, collision="mrt", streami
 def copy_ceiling(steps, runs):
     """Hand-written streaming kernels with no arithmetic (pflbm_hbm_copy):
     2 GiB plain copies with 4- and 16-byte accesses, and the FP32 step's own
-    access pattern (43 rows of N floats read and written, N = the rising-bubble
-    lattice).  GB/s counts bytes read plus bytes written."""
+    access pattern (43 rows of N floats read and written, cached or
+    non-temporal loads, N = the rising-bubble lattice and the 384^3 drop).
+    GB/s counts bytes read plus bytes written."""
     import ctypes as C
 
     import torch
@@ -170,7 +171,10 @@ def copy_ceiling(steps, runs):
     out = {}
     cases = [("w4_2GiB", "w4", 1 << 31), ("w16_2GiB", "w16", 1 << 31),
              ("w16_cached_2GiB", "w16_cached", 1 << 31),
-             ("soa43_fp32_step_pattern_128x512x128", "soa43", 43 * 4 * 128 * 512 * 128)]
+             ("soa43_fp32_step_pattern_128x512x128", "soa43", 43 * 4 * 128 * 512 * 128),
+             ("soa43_nt_fp32_step_pattern_128x512x128", "soa43_nt", 43 * 4 * 128 * 512 * 128),
+             ("soa43_fp32_step_pattern_384x384x384", "soa43", 43 * 4 * 384 ** 3),
+             ("soa43_nt_fp32_step_pattern_384x384x384", "soa43_nt", 43 * 4 * 384 ** 3)]
     for name, form, nbytes in cases:
         a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

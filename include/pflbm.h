@@ -334,9 +334,16 @@ pflbm_status pflbm_adjoint_grads(pflbm_ctx* ctx, double out_host[3]);
  *                          populations + the phase field); one thread per cell
  *                          loads its 43 values (cached, all in flight) and
  *                          stores them to the same rows of d_dst (non-temporal)
+ *   PFLBM_COPY_SOA43_NT    the same with non-temporal loads
  * Returns PFLBM_ERR_ARG for a bad pointer, size or form (nothing enqueued).
  * ------------------------------------------------------------------------- */
-enum { PFLBM_COPY_W4 = 0, PFLBM_COPY_W16 = 1, PFLBM_COPY_W16_CACHED = 2, PFLBM_COPY_SOA43 = 3 };
+enum {
+  PFLBM_COPY_W4 = 0,
+  PFLBM_COPY_W16 = 1,
+  PFLBM_COPY_W16_CACHED = 2,
+  PFLBM_COPY_SOA43 = 3,
+  PFLBM_COPY_SOA43_NT = 4
+};
 pflbm_status pflbm_hbm_copy(const void* d_src, void* d_dst, size_t bytes, int32_t form, void* hip_stream);
 
 const char* pflbm_status_string(pflbm_status s);

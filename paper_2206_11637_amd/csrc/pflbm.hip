@@ -988,13 +988,18 @@ pflbm_status pflbm_hbm_copy(const void* d_src, void* d_dst, size_t bytes, int32_
                          static_cast<const u32x4*>(d_src), static_cast<u32x4*>(d_dst), n);
       break;
     }
-    case PFLBM_COPY_SOA43: {
+    case PFLBM_COPY_SOA43:
+    case PFLBM_COPY_SOA43_NT: {
       // 43 rows of N floats on each side
       if (bytes % (43 * 4) != 0) return PFLBM_ERR_ARG;
       const long long N = (long long)(bytes / (43 * 4));
       if ((N + 255) / 256 >= (1ll << 31)) return PFLBM_ERR_ARG;
-      hipLaunchKernelGGL((k_copy_soa<42>), grid(N, 256), blk, 0, s, static_cast<const float*>(d_src),
-                         static_cast<float*>(d_dst), N);
+      if (form == PFLBM_COPY_SOA43)
+        hipLaunchKernelGGL((k_copy_soa<42, false>), grid(N, 256), blk, 0, s, static_cast<const float*>(d_src),
+                           static_cast<float*>(d_dst), N);
+      else
+        hipLaunchKernelGGL((k_copy_soa<42, true>), grid(N, 256), blk, 0, s, static_cast<const float*>(d_src),
+                           static_cast<float*>(d_dst), N);
       break;
     }
     default:

@@ -357,3 +357,22 @@ def test_binding_refuses_mismatched_buffers_on_the_host():
             check_buffer(t, cpu, "x", **kw)
     with pytest.raises(ValueError, match="simulation is on"):
         check_buffer(ok, torch.device("cuda:0"), "x")
+
+
+def test_copy_probe_refuses_bad_arguments_before_any_launch():
+    """pflbm_hbm_copy checks pointers, alignment, size and form on the host
+    and enqueues nothing when one is wrong (stand-in addresses, never
+    dereferenced)."""
+    L, lib = _lib()
+    src, dst = C.c_void_p(1 << 20), C.c_void_p(1 << 21)
+    soa = 43 * 4 * 256
+    err = L.PFLBM_ERR_ARG
+    assert lib.pflbm_hbm_copy(None, dst, 1024, L.COPY_FORMS["w4"], None) == err
+    assert lib.pflbm_hbm_copy(src, src, 1024, L.COPY_FORMS["w4"], None) == err
+    assert lib.pflbm_hbm_copy(src, dst, 0, L.COPY_FORMS["w4"], None) == err
+    assert lib.pflbm_hbm_copy(C.c_void_p((1 << 20) + 4), dst, 1024, L.COPY_FORMS["w16"], None) == err
+    assert lib.pflbm_hbm_copy(src, dst, 1000, L.COPY_FORMS["w16"], None) == err
+    for form in ("soa43", "soa43_nt"):
+        assert lib.pflbm_hbm_copy(src, dst, soa + 16, L.COPY_FORMS[form], None) == err
+    assert lib.pflbm_hbm_copy(src, dst, 1024, max(L.COPY_FORMS.values()) + 1, None) == err
+    assert lib.pflbm_hbm_copy(src, dst, 1024, -1, None) == err
