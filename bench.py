@@ -6,8 +6,10 @@ hydrodynamics, forces, stencils, bounce-back) followed by the phase-field
 update.  The headline workload is the rising-bubble lattice 128 x 512 x 128
 (8.4 M cells, six bounce-back faces) in FP64, the arithmetic of the paper's
 runs; the line also carries the FP32 and FP16-storage forms (each with its
-own roofline block), a hand-written streaming-copy ceiling, the reverse-mode
-cost and the gradient error of the reduced-precision forms against FP64.
+own roofline block), a hand-written streaming-copy ceiling, one GPU's z-slab
+of the 384^3 drop with the pack of its faces for the slab exchange, the
+reverse-mode cost and the gradient error of the reduced-precision forms
+against FP64.
 
   python bench.py [--steps K] [--warmup W] [--runs R] [--no-cpu-baseline]
                   [--no-forms] [--only NAME,NAME] [--precision P]
@@ -151,6 +153,52 @@ def time_form(name, wl, precision, steps, warmup, runs, collision="mrt", streami
                roofline_alu=roofline_alu(name, cells, cell_avg),
                mass=float(r[0]))
     del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def halo_pack(wl, steps, warmup, runs, launches=100):
+    """The z-slab shard's step (FP32) and the pack of its two faces for the
+    slab exchange (pflbm_pack_faces: the populations with c_z = -1 at plane 0
+    and c_z = +1 at plane nz - 1 into one staging buffer).  The packs are
+    queued behind a run of steps so that they execute back to back; their
+    HIP-event time over `launches` packs, median of `runs`."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2206_11637_amd.sim import from_workload
+    sim = from_workload(wl, precision="fp32")
+    sim.step(warmup)
+    buf = sim.pack_faces()
+    nbytes = buf.numel() * buf.element_size()
+    need = C.c_size_t()
+    args = (sim.ctx, C.c_void_p(buf.data_ptr()), C.c_size_t(nbytes), C.byref(need))
+    steps_ms, pack_ms = [], []
+    for _ in range(runs):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        torch.cuda.synchronize()
+        e[0].record(sim.stream)
+        sim.step(steps)
+        e[1].record(sim.stream)
+        for _ in range(launches):
+            st = sim.lib.pflbm_pack_faces(*args)
+            if st:
+                raise RuntimeError(f"pflbm_pack_faces failed with status {st}")
+        e[2].record(sim.stream)
+        torch.cuda.synchronize()
+        steps_ms.append(e[0].elapsed_time(e[1]) / steps)
+        pack_ms.append(e[1].elapsed_time(e[2]) / launches)
+    step = statistics.median(steps_ms)
+    pack = statistics.median(pack_ms)
+    gbps = 2 * nbytes / (pack * 1e-3) / 1e9
+    out = dict(ms_per_step=round(step, 5), mlups=round(wl.cells / (step * 1e-3) / 1e6, 1),
+               pack_ms=round(pack, 6), pack_rows_per_face=int(buf.shape[1]),
+               face_cells=int(buf.shape[2] * buf.shape[3]), pack_bytes_read=nbytes,
+               pack_bytes_written=nbytes, pack_GBps=round(gbps, 1),
+               pack_frac_of_8TBps=round(gbps / HBM_PEAK_GBPS, 4),
+               pack_over_step=round(pack / step, 5), launches=launches, runs=runs)
+    del sim, buf
     torch.cuda.empty_cache()
     return out
 
@@ -528,6 +576,9 @@ def main():
         # as many steps as the full drop: the cut drop, wrapped in z, turns
         # non-finite after ~1k steps at M = 0.01
         form(n, time_form, n, shard, "fp32", half, Wm, R)
+        # the same shard with the pack of its two faces for the slab exchange
+        n = "fp32_halo_pack_of_shard_384x384x48"
+        form(n, halo_pack, shard, half, Wm, R)
         del shard
         del wl2
         if slow:

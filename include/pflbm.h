@@ -322,6 +322,28 @@ pflbm_status pflbm_adjoint_init(pflbm_ctx* ctx, const double* d_u0, double* d_dp
 pflbm_status pflbm_adjoint_grads(pflbm_ctx* ctx, double out_host[3]);
 
 /* ---------------------------------------------------------------------------
+ * Halo pack of a z-slab decomposition (the part of the multi-GPU step that one
+ * GPU can run).  With the lattice split into slabs along z, each step pulls
+ * across a slab face exactly the populations that the streaming step (paper
+ * sec. "Lattice Boltzmann equations", eq. streaming) moves from one plane to
+ * the next along z: those with c_z = -1 stored at plane 0 (bound for the slab
+ * below) and those with c_z = +1 stored at plane nz - 1 (bound for the slab
+ * above).  Copies them from the current state into d_dst on the context's
+ * stream, asynchronously.  Layout of d_dst: face 0 (plane 0, c_z = -1) then
+ * face 1 (plane nz - 1, c_z = +1); within a face first the h rows, then the g
+ * rows, each in the direction order of pflbm_lattice / pflbm_phase_q; a row is
+ * the nx * ny values of one population on that plane, x fastest, in the
+ * storage type exactly as the state holds them (FP64, FP32, or FP16 with its
+ * scale and shift, as in a saved state).  Rows per face: 5 + 9 (D3Q15 phase
+ * lattice) or 9 + 9 (D3Q27).  *bytes_needed (required) receives the size
+ * 2 x rows x nx x ny x storage size; with d_dst NULL nothing else happens.
+ * Returns PFLBM_ERR_ARG for a NULL bytes_needed or dst_bytes below the size,
+ * PFLBM_ERR_STATE without an initialised state or with PFLBM_STREAM_AA (whose
+ * slots depend on the step parity; only the two-buffer scheme is packed).
+ * ------------------------------------------------------------------------- */
+pflbm_status pflbm_pack_faces(pflbm_ctx* ctx, void* d_dst, size_t dst_bytes, size_t* bytes_needed);
+
+/* ---------------------------------------------------------------------------
  * Measurement helper (not part of the method): the HBM ceiling of a kernel
  * that only streams data.  Copies `bytes` from d_src to d_dst (device memory,
  * both 16-byte aligned, not overlapping, bytes a multiple of 16) on

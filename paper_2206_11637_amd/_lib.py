@@ -65,6 +65,7 @@ SIGNATURES = {
     "pflbm_adjoint_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pflbm_adjoint_grads": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pflbm_hbm_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]),
+    "pflbm_pack_faces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "pflbm_status_string": (C.c_char_p, [C.c_int]),
     "pflbm_last_error": (C.c_char_p, [C.c_void_p]),
 }

@@ -1377,6 +1377,34 @@ __global__ __launch_bounds__(256) void k_phi_from_f64(const double* __restrict__
   if (i < N) out[i] = (mask && mask[i]) ? R(0) : R(in[i]);
 }
 
+// ---- halo pack of the z-slab decomposition ---------------------------------
+// Split along z into slabs, each step needs from a neighbouring slab the
+// populations that stream across the shared face: those with c_z = -1 stored
+// at plane 0 go to the slab below, those with c_z = +1 stored at plane nz - 1
+// to the slab above.  k_pack_faces copies them into a staging buffer, row by
+// row (blockIdx.y = face * rows + row): face 0 then face 1, within a face the
+// h rows then the g rows, each the nx * ny values of one population on that
+// plane in the storage type, unchanged.
+struct PackRows {
+  int n;                     // rows per face
+  int nh;                    // of which the first nh are h rows
+  int pop[2][Q_H + Q_G];     // population index of each row, per face
+};
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_pack_faces(const S* __restrict__ h, const S* __restrict__ g,
+                                                    S* __restrict__ dst, long long N, long long nxy,
+                                                    int nz, PackRows r) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nxy) return;
+  const int row = blockIdx.y;
+  const int face = row >= r.n ? 1 : 0;
+  const int k = row - face * r.n;
+  const long long plane = face ? (long long)(nz - 1) * nxy : 0;
+  const S* src = (k < r.nh ? h : g) + (long long)r.pop[face][k] * N + plane + e;
+  dst[(long long)row * nxy + e] = *src;
+}
+
 // phi (compute precision) -> FP64
 template <typename R>
 __global__ __launch_bounds__(256) void k_phi_to_f64(const R* __restrict__ phi, long long N,

@@ -743,6 +743,33 @@ pflbm_status params_ok(const pflbm_params* p, std::string& why) {
   return PFLBM_OK;
 }
 
+// rows of the halo pack: per face the h, then the g directions with c_z = -1
+// (face 0, plane 0) or +1 (face 1, plane nz - 1), in table order
+PackRows pack_rows() {
+  PackRows r{};
+  for (int f = 0; f < 2; ++f) {
+    const int dz = f ? 1 : -1;
+    int n = 0;
+    for (int i = 0; i < Q_H; ++i)
+      if (ch(i).z == dz) r.pop[f][n++] = i;
+    r.nh = n;
+    for (int i = 0; i < Q_G; ++i)
+      if (cg(i).z == dz) r.pop[f][n++] = i;
+    r.n = n;
+  }
+  return r;
+}
+
+template <typename S>
+pflbm_status do_pack_faces(pflbm_ctx* c, void* dst) {
+  const PackRows r = pack_rows();
+  const long long nxy = (long long)c->d.nx * c->d.ny;
+  const dim3 grid((unsigned)((nxy + 255) / 256), (unsigned)(2 * r.n));
+  hipLaunchKernelGGL(k_pack_faces<S>, grid, dim3(256), 0, c->stream, pop_h<S>(c, c->pcur), pop_g<S>(c, c->pcur),
+                     static_cast<S*>(dst), c->L.N, nxy, c->d.nz, r);
+  return check_hip(c, hipGetLastError(), "pflbm_pack_faces");
+}
+
 }  // namespace
 
 // ============================================================================
@@ -859,6 +886,21 @@ pflbm_status pflbm_read_phi(pflbm_ctx* c, double* d_phi) {
   if (!d_phi) return fail(c, PFLBM_ERR_ARG, "output is NULL");
   if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
   DISPATCH(c, do_read_phi, c, d_phi);
+}
+
+pflbm_status pflbm_pack_faces(pflbm_ctx* c, void* dst, size_t dst_bytes, size_t* bytes_needed) {
+  if (!c) return PFLBM_ERR_ARG;
+  if (!bytes_needed) return fail(c, PFLBM_ERR_ARG, "pflbm_pack_faces: bytes_needed is NULL");
+  const size_t need = (size_t)2 * pack_rows().n * (size_t)c->d.nx * (size_t)c->d.ny * store_size(c->d.precision);
+  *bytes_needed = need;
+  if (!dst) return PFLBM_OK;
+  if (dst_bytes < need)
+    return fail(c, PFLBM_ERR_ARG, "pflbm_pack_faces: the buffer holds " + std::to_string(dst_bytes) +
+                                      " bytes, the two faces need " + std::to_string(need));
+  if (c->d.streaming != PFLBM_STREAM_AB)
+    return fail(c, PFLBM_ERR_STATE, "pflbm_pack_faces: needs the two-buffer scheme PFLBM_STREAM_AB");
+  if (!c->initialised) return fail(c, PFLBM_ERR_STATE, "not initialised");
+  DISPATCH(c, do_pack_faces, c, dst);
 }
 
 pflbm_status pflbm_read_populations(pflbm_ctx* c, double* h, double* g) {

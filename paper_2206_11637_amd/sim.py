@@ -26,6 +26,10 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+# storage dtype of the populations of each precision form
+_STORAGE_DTYPES = {"fp64": torch.float64, "fp32": torch.float32, "fp16s": torch.float16}
+
+
 def check_buffer(t, device, name: str, *, numel: Optional[int] = None, dtype=None,
                  min_bytes: Optional[int] = None) -> torch.Tensor:
     """Refuse, before any library call, a caller buffer the kernels would
@@ -190,6 +194,23 @@ class Simulation:
         self._run("pflbm_read_populations", self.lib.pflbm_read_populations, _ptr(h), _ptr(g),
                   keep=(h, g))
         return h, g
+
+    def pack_faces(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """The populations that stream across the two z faces of the lattice,
+        as a z-slab of a larger one would send them (pflbm_pack_faces): a
+        (2, rows, ny, nx) tensor in the storage dtype, face 0 (plane 0,
+        c_z = -1) then face 1 (plane nz - 1, c_z = +1), h rows then g rows."""
+        need = C.c_size_t()
+        check(self.lib.pflbm_pack_faces(self.ctx, None, 0, C.byref(need)), self.ctx, "pflbm_pack_faces")
+        dt = _STORAGE_DTYPES[self.precision]
+        nz, ny, nx = self.shape
+        rows = need.value // (2 * ny * nx * torch.empty((), dtype=dt).element_size())
+        if out is None:
+            out = torch.empty((2, rows, ny, nx), dtype=dt, device=self.device)
+        check_buffer(out, self.device, "face pack", dtype=dt, min_bytes=need.value)
+        self._run("pflbm_pack_faces", self.lib.pflbm_pack_faces, _ptr(out),
+                  C.c_size_t(out.numel() * out.element_size()), C.byref(need), keep=(out,))
+        return out
 
     def reduce(self) -> np.ndarray:
         out = (C.c_double * 5)()

@@ -376,3 +376,35 @@ def test_copy_probe_refuses_bad_arguments_before_any_launch():
         assert lib.pflbm_hbm_copy(src, dst, soa + 16, L.COPY_FORMS[form], None) == err
     assert lib.pflbm_hbm_copy(src, dst, 1024, max(L.COPY_FORMS.values()) + 1, None) == err
     assert lib.pflbm_hbm_copy(src, dst, 1024, -1, None) == err
+
+
+@pytest.mark.parametrize("precision, size", [(0, 8), (1, 4), (2, 2)])
+def test_face_pack_size_and_refusals_on_the_host(precision, size):
+    """pflbm_pack_faces reports 2 faces x (5 h + 9 g rows with c_z = -/+1) x
+    nx x ny values of the storage size and refuses, before any launch, a
+    missing size pointer, a short buffer, the in-place scheme and a state that
+    was never initialised (stand-in addresses, never dereferenced)."""
+    L, lib = _lib()
+    from paper_2206_11637_amd.sim import lattice
+    c_h, c_g = lattice(int(lib.pflbm_phase_q()))[0], lattice(27)[0]
+    rows = int((c_h[:, 2] == 1).sum() + (c_g[:, 2] == 1).sum())
+    assert rows == ((9 if lib.pflbm_phase_q() == 27 else 5) + 9)
+    d = L.Desc(12, 7, 5, 7, precision, 1, 0)
+    n = lib.pflbm_workspace_bytes(C.byref(d))
+    ctx = C.c_void_p()
+    assert lib.pflbm_create(C.byref(d), C.c_void_p(4096), n, None, C.byref(ctx)) == 0
+    need = C.c_size_t()
+    assert lib.pflbm_pack_faces(None, None, 0, C.byref(need)) == L.PFLBM_ERR_ARG
+    assert lib.pflbm_pack_faces(ctx, None, 0, None) == L.PFLBM_ERR_ARG
+    assert lib.pflbm_pack_faces(ctx, None, 0, C.byref(need)) == 0
+    assert need.value == 2 * rows * 12 * 7 * size
+    dst = C.c_void_p(1 << 20)
+    assert lib.pflbm_pack_faces(ctx, dst, need.value - 1, C.byref(need)) == L.PFLBM_ERR_ARG
+    assert lib.pflbm_pack_faces(ctx, dst, need.value, C.byref(need)) == L.PFLBM_ERR_STATE
+    assert lib.pflbm_destroy(ctx) == 0
+    daa = L.Desc(12, 7, 5, 7, precision, 1, 0, L.STREAMING["aa"])
+    n = lib.pflbm_workspace_bytes(C.byref(daa))
+    assert lib.pflbm_create(C.byref(daa), C.c_void_p(4096), n, None, C.byref(ctx)) == 0
+    assert lib.pflbm_pack_faces(ctx, dst, need.value, C.byref(need)) == L.PFLBM_ERR_STATE
+    assert "PFLBM_STREAM_AB" in lib.pflbm_last_error(ctx).decode()
+    assert lib.pflbm_destroy(ctx) == 0
