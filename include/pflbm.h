@@ -337,9 +337,11 @@ pflbm_status pflbm_adjoint_grads(pflbm_ctx* ctx, double out_host[3]);
  * scale and shift, as in a saved state).  Rows per face: 5 + 9 (D3Q15 phase
  * lattice) or 9 + 9 (D3Q27).  *bytes_needed (required) receives the size
  * 2 x rows x nx x ny x storage size; with d_dst NULL nothing else happens.
- * Returns PFLBM_ERR_ARG for a NULL bytes_needed or dst_bytes below the size,
- * PFLBM_ERR_STATE without an initialised state or with PFLBM_STREAM_AA (whose
- * slots depend on the step parity; only the two-buffer scheme is packed).
+ * d_dst is device memory owned by the caller, aligned to the storage size.
+ * Returns PFLBM_ERR_ARG for a NULL bytes_needed, a misaligned d_dst or
+ * dst_bytes below the size, PFLBM_ERR_STATE without an initialised state or
+ * with PFLBM_STREAM_AA (whose slots depend on the step parity; only the
+ * two-buffer scheme is packed).
  * ------------------------------------------------------------------------- */
 pflbm_status pflbm_pack_faces(pflbm_ctx* ctx, void* d_dst, size_t dst_bytes, size_t* bytes_needed);
 

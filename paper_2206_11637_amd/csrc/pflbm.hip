@@ -894,6 +894,8 @@ pflbm_status pflbm_pack_faces(pflbm_ctx* c, void* dst, size_t dst_bytes, size_t*
   const size_t need = (size_t)2 * pack_rows().n * (size_t)c->d.nx * (size_t)c->d.ny * store_size(c->d.precision);
   *bytes_needed = need;
   if (!dst) return PFLBM_OK;
+  if (reinterpret_cast<uintptr_t>(dst) % store_size(c->d.precision) != 0)
+    return fail(c, PFLBM_ERR_ARG, "pflbm_pack_faces: the buffer is not aligned to the storage size");
   if (dst_bytes < need)
     return fail(c, PFLBM_ERR_ARG, "pflbm_pack_faces: the buffer holds " + std::to_string(dst_bytes) +
                                       " bytes, the two faces need " + std::to_string(need));

@@ -400,6 +400,9 @@ def test_face_pack_size_and_refusals_on_the_host(precision, size):
     assert need.value == 2 * rows * 12 * 7 * size
     dst = C.c_void_p(1 << 20)
     assert lib.pflbm_pack_faces(ctx, dst, need.value - 1, C.byref(need)) == L.PFLBM_ERR_ARG
+    if size > 1:
+        assert lib.pflbm_pack_faces(ctx, C.c_void_p((1 << 20) + 1), need.value,
+                                    C.byref(need)) == L.PFLBM_ERR_ARG
     assert lib.pflbm_pack_faces(ctx, dst, need.value, C.byref(need)) == L.PFLBM_ERR_STATE
     assert lib.pflbm_destroy(ctx) == 0
     daa = L.Desc(12, 7, 5, 7, precision, 1, 0, L.STREAMING["aa"])
