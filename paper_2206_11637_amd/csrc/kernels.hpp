@@ -861,6 +861,15 @@ __device__ __forceinline__ void lds_settled() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
+// every global-to-LDS load issued so far by this wave has landed (vmcnt 0):
+// their LDS writes are tracked by the vector memory counter only, and the
+// compiler places its own waits for them inside the branches that read the
+// slots, so a wave whose own cells are all skipped would read its ring
+// cells' slots without one
+__device__ __forceinline__ void dma_settled() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 // one element per lane from global memory straight into LDS: lane l's value
 // lands in the dword at lds_wave + l (an FP16 value in its low half); the
 // size is written as a literal (a template-dependent size crashes this
@@ -987,6 +996,7 @@ void k_step_dma(StepArgs<S> a) {
   PlaneState<R> s0, s1, s2;
   issue(t.z0 - 1, s0);
   issue(t.z0, s1);
+  dma_settled();
   phi_plane(t.z0 - 1, s0);
   lds_settled();
   issue(t.z0 + 1, s2);         // into the slots of plane z0 - 1, consumed above
@@ -1001,7 +1011,8 @@ void k_step_dma(StepArgs<S> a) {
   }
   for (int z = t.z0; z < t.z1; ++z) {
     // s0: plane z (phi in the ring, raw h in LDS, raw g in registers);
-    // s1: plane z + 1 (pulls in flight)
+    // s1: plane z + 1 (pulls in flight, landed after the wait)
+    dma_settled();
     phi_plane(z + 1, s1);
     __syncthreads();
     const bool work = active && !s0.skip;
