@@ -50,13 +50,13 @@ STEP_BYTES_D3Q27 = {"fp64": 880, "fp32": 440, "fp16s": 224}
 # same box (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE), keyed by form; taken for
 # the current kernel (profiles/k_step_hbm_traffic.txt) and re-measured
 # whenever it changes.  Forms without an entry report null.
-TRAFFIC = {"fp64_rising_bubble_128x512x128": 6.0922e9,
-           "fp32_rising_bubble_128x512x128": 3.2426e9,
-           "fp16s_rising_bubble_128x512x128": 1.5513e9,
-           "fp32_d3q27_phase_rising_bubble_128x512x128": 4.2848e9,
-           "fp32_drop_impact_384^3": 2.3258e10,
-           "fp16s_drop_impact_384^3": 1.1178e10,
-           "fp32_in_place_aa_rising_bubble_128x512x128": 3.0633e9}
+TRAFFIC = {"fp64_rising_bubble_128x512x128": 6.0920e9,
+           "fp32_rising_bubble_128x512x128": 3.2388e9,
+           "fp16s_rising_bubble_128x512x128": 1.5514e9,
+           "fp32_d3q27_phase_rising_bubble_128x512x128": 4.2801e9,
+           "fp32_drop_impact_384^3": 2.3102e10,
+           "fp16s_drop_impact_384^3": 1.1193e10,
+           "fp32_in_place_aa_rising_bubble_128x512x128": 3.0657e9}
 TRAFFIC_UNIT = "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
 # Vector ALU instructions per wave and z plane of the step kernel (= per cell
 # for one lane), rocprofv3 SQ_INSTS_VALU over SQ_WAVES and the planes each wave
