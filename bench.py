@@ -203,6 +203,24 @@ def halo_pack(wl, steps, warmup, runs, launches=100):
     return out
 
 
+def attach_copy_ceiling(forms):
+    """Each FP32 two-buffer form's achieved bandwidth over the faster of the
+    two step-pattern copies (cached or non-temporal loads) measured on the
+    same lattice in the same run: roofline.vs_copy_ceiling."""
+    cc = forms.get("hbm_copy_ceiling")
+    if not isinstance(cc, dict) or "error" in cc:
+        return
+    lattices = {"128x512x128": "fp32_rising_bubble_128x512x128", "384x384x384": "fp32_drop_impact_384^3"}
+    for lat, name in lattices.items():
+        f = forms.get(name)
+        rates = [v["GBps"] for k, v in cc.items() if k.endswith(f"step_pattern_{lat}")]
+        if not f or "roofline" not in f or not rates:
+            continue
+        ceiling = max(rates)
+        f["roofline"]["copy_ceiling_GBps"] = ceiling
+        f["roofline"]["vs_copy_ceiling"] = round(f["roofline"]["achieved"] / ceiling, 4)
+
+
 def copy_ceiling(steps, runs):
     """Hand-written streaming kernels with no arithmetic (pflbm_hbm_copy):
     2 GiB plain copies with 4- and 16-byte accesses, and the FP32 step's own
@@ -601,6 +619,7 @@ def main():
                  args.adj_steps, 10, 64, column_level(wl4, 64), W.config4(scale=2),
                  conditioning=True)
             del wl4
+    attach_copy_ceiling(forms)
     cpu = None
     if not args.no_cpu_baseline and not only:
         log("bench: cpu baseline (oracle)")

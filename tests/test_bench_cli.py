@@ -68,3 +68,26 @@ def test_reported_instruction_counts_match_the_committed_counter_summary():
     r = B.roofline_alu("fp16s_drop_impact_384^3", 56623104, 3.0)
     assert r["bound"] == "alu" and abs(r["achieved"] - 1312.9 * 56623104 / 64 / 3e-3 / 1e9) < 0.1
     assert B.roofline_alu("fp64_rising_bubble_128x512x128", 8388608, 1.0) is None
+
+
+def test_fp32_forms_are_set_against_the_faster_step_pattern_copy():
+    """attach_copy_ceiling divides each FP32 two-buffer form's achieved rate by
+    the faster step-pattern copy of its own lattice, and leaves the line alone
+    when the copy leg is missing or failed."""
+    sys.path.insert(0, ROOT)
+    import bench as B
+    forms = {"hbm_copy_ceiling": {
+        "soa43_fp32_step_pattern_128x512x128": {"GBps": 5600.0},
+        "soa43_nt_fp32_step_pattern_128x512x128": {"GBps": 6000.0},
+        "soa43_fp32_step_pattern_384x384x384": {"GBps": 5200.0},
+        "soa43_nt_fp32_step_pattern_384x384x384": {"GBps": 5250.0},
+        "w4_2GiB": {"GBps": 6300.0}},
+        "fp32_rising_bubble_128x512x128": {"roofline": {"achieved": 4500.0}},
+        "fp32_drop_impact_384^3": {"roofline": {"achieved": 4462.5}}}
+    B.attach_copy_ceiling(forms)
+    assert forms["fp32_rising_bubble_128x512x128"]["roofline"]["vs_copy_ceiling"] == 0.75
+    assert forms["fp32_rising_bubble_128x512x128"]["roofline"]["copy_ceiling_GBps"] == 6000.0
+    assert forms["fp32_drop_impact_384^3"]["roofline"]["vs_copy_ceiling"] == 0.85
+    bad = {"hbm_copy_ceiling": {"error": "x"}, "fp32_drop_impact_384^3": {"roofline": {"achieved": 1.0}}}
+    B.attach_copy_ceiling(bad)
+    assert "vs_copy_ceiling" not in bad["fp32_drop_impact_384^3"]["roofline"]
