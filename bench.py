@@ -203,17 +203,22 @@ def halo_pack(wl, steps, warmup, runs, launches=100):
     return out
 
 
-def attach_copy_ceiling(forms):
-    """Each FP32 two-buffer form's achieved bandwidth over the faster of the
-    two step-pattern copies (cached or non-temporal loads) measured on the
-    same lattice in the same run: roofline.vs_copy_ceiling."""
+def attach_copy_ceiling(forms, extra=None):
+    """Each two-buffer FP32 and FP64 form's achieved bandwidth over the faster
+    of the two step-pattern copies of its element size (cached or
+    non-temporal loads) measured on the same lattice in the same run:
+    roofline.vs_copy_ceiling.  extra: more forms by name (the headline)."""
     cc = forms.get("hbm_copy_ceiling")
     if not isinstance(cc, dict) or "error" in cc:
         return
-    lattices = {"128x512x128": "fp32_rising_bubble_128x512x128", "384x384x384": "fp32_drop_impact_384^3"}
-    for lat, name in lattices.items():
-        f = forms.get(name)
-        rates = [v["GBps"] for k, v in cc.items() if k.endswith(f"step_pattern_{lat}")]
+    every = dict(forms)
+    every.update(extra or {})
+    targets = {"fp32_rising_bubble_128x512x128": "fp32_step_pattern_128x512x128",
+               "fp32_drop_impact_384^3": "fp32_step_pattern_384x384x384",
+               "fp64_rising_bubble_128x512x128": "fp64_step_pattern_128x512x128"}
+    for name, pattern in targets.items():
+        f = every.get(name)
+        rates = [v["GBps"] for k, v in cc.items() if k.endswith(pattern)]
         if not f or "roofline" not in f or not rates:
             continue
         ceiling = max(rates)
@@ -225,8 +230,9 @@ def copy_ceiling(steps, runs):
     """Hand-written streaming kernels with no arithmetic (pflbm_hbm_copy):
     2 GiB plain copies with 4- and 16-byte accesses, and the FP32 step's own
     access pattern (43 rows of N floats read and written, cached or
-    non-temporal loads, N = the rising-bubble lattice and the 384^3 drop).
-    GB/s counts bytes read plus bytes written."""
+    non-temporal loads, N = the rising-bubble lattice and the 384^3 drop) and
+    the FP64 step's (43 rows of N doubles, the rising-bubble lattice).  GB/s
+    counts bytes read plus bytes written."""
     import ctypes as C
 
     import torch
@@ -240,7 +246,9 @@ def copy_ceiling(steps, runs):
              ("soa43_fp32_step_pattern_128x512x128", "soa43", 43 * 4 * 128 * 512 * 128),
              ("soa43_nt_fp32_step_pattern_128x512x128", "soa43_nt", 43 * 4 * 128 * 512 * 128),
              ("soa43_fp32_step_pattern_384x384x384", "soa43", 43 * 4 * 384 ** 3),
-             ("soa43_nt_fp32_step_pattern_384x384x384", "soa43_nt", 43 * 4 * 384 ** 3)]
+             ("soa43_nt_fp32_step_pattern_384x384x384", "soa43_nt", 43 * 4 * 384 ** 3),
+             ("soa43_f64_fp64_step_pattern_128x512x128", "soa43_f64", 43 * 8 * 128 * 512 * 128),
+             ("soa43_f64_nt_fp64_step_pattern_128x512x128", "soa43_f64_nt", 43 * 8 * 128 * 512 * 128)]
     for name, form, nbytes in cases:
         a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -619,7 +627,7 @@ def main():
                  args.adj_steps, 10, 64, column_level(wl4, 64), W.config4(scale=2),
                  conditioning=True)
             del wl4
-    attach_copy_ceiling(forms)
+    attach_copy_ceiling(forms, {head_name: main_form} if main_form else None)
     cpu = None
     if not args.no_cpu_baseline and not only:
         log("bench: cpu baseline (oracle)")

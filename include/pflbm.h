@@ -359,6 +359,9 @@ pflbm_status pflbm_pack_faces(pflbm_ctx* ctx, void* d_dst, size_t dst_bytes, siz
  *                          loads its 43 values (cached, all in flight) and
  *                          stores them to the same rows of d_dst (non-temporal)
  *   PFLBM_COPY_SOA43_NT    the same with non-temporal loads
+ *   PFLBM_COPY_SOA43_F64, PFLBM_COPY_SOA43_F64_NT
+ *                          the same two with 43 rows of N doubles (the FP64
+ *                          step's pattern)
  * Returns PFLBM_ERR_ARG for a bad pointer, size or form (nothing enqueued).
  * ------------------------------------------------------------------------- */
 enum {
@@ -366,7 +369,9 @@ enum {
   PFLBM_COPY_W16 = 1,
   PFLBM_COPY_W16_CACHED = 2,
   PFLBM_COPY_SOA43 = 3,
-  PFLBM_COPY_SOA43_NT = 4
+  PFLBM_COPY_SOA43_NT = 4,
+  PFLBM_COPY_SOA43_F64 = 5,
+  PFLBM_COPY_SOA43_F64_NT = 6
 };
 pflbm_status pflbm_hbm_copy(const void* d_src, void* d_dst, size_t bytes, int32_t form, void* hip_stream);
 

@@ -15,7 +15,8 @@ COLLISIONS = {"bgk": 0, "mrt": 1}
 STREAMING = {"ab": 0, "aa": 1}
 FORCING = {"first": 0, "guo": 1}
 STATES_WRITE_SRC_PHI, STATES_SKIP_DST_PHI = 1, 2
-COPY_FORMS = {"w4": 0, "w16": 1, "w16_cached": 2, "soa43": 3, "soa43_nt": 4}
+COPY_FORMS = {"w4": 0, "w16": 1, "w16_cached": 2, "soa43": 3, "soa43_nt": 4, "soa43_f64": 5,
+              "soa43_f64_nt": 6}
 
 
 class Desc(C.Structure):

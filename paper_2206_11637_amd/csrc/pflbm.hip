@@ -1046,6 +1046,20 @@ pflbm_status pflbm_hbm_copy(const void* d_src, void* d_dst, size_t bytes, int32_
                            static_cast<float*>(d_dst), N);
       break;
     }
+    case PFLBM_COPY_SOA43_F64:
+    case PFLBM_COPY_SOA43_F64_NT: {
+      // 43 rows of N doubles on each side
+      if (bytes % (43 * 8) != 0) return PFLBM_ERR_ARG;
+      const long long N = (long long)(bytes / (43 * 8));
+      if ((N + 255) / 256 >= (1ll << 31)) return PFLBM_ERR_ARG;
+      if (form == PFLBM_COPY_SOA43_F64)
+        hipLaunchKernelGGL((k_copy_soa<42, false, double>), grid(N, 256), blk, 0, s,
+                           static_cast<const double*>(d_src), static_cast<double*>(d_dst), N);
+      else
+        hipLaunchKernelGGL((k_copy_soa<42, true, double>), grid(N, 256), blk, 0, s,
+                           static_cast<const double*>(d_src), static_cast<double*>(d_dst), N);
+      break;
+    }
     default:
       return PFLBM_ERR_ARG;
   }

@@ -6,7 +6,7 @@
 //                (W = 4, 8 or 16; cached or non-temporal)
 // k_copy_soa     the step's access pattern without its arithmetic: one thread
 //                per cell reads Q structure-of-arrays rows at its own index
-//                (4-byte accesses, all Q loads in flight; cached or
+//                (4- or 8-byte accesses, all Q loads in flight; cached or
 //                non-temporal) and writes them to Q other rows
 //                (non-temporal), plus one extra row read and one written (the
 //                phase field's two streams)
@@ -38,12 +38,12 @@ __global__ __launch_bounds__(256) void k_copy_lines(const T* __restrict__ src, T
   }
 }
 
-template <int Q, bool NT_LOAD>
-__global__ __launch_bounds__(256) void k_copy_soa(const float* __restrict__ src, float* __restrict__ dst,
+template <int Q, bool NT_LOAD, typename T = float>
+__global__ __launch_bounds__(256) void k_copy_soa(const T* __restrict__ src, T* __restrict__ dst,
                                                   long long N) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
   if (idx >= N) return;
-  float v[Q + 1];
+  T v[Q + 1];
 #pragma unroll
   for (int q = 0; q <= Q; ++q) v[q] = NT_LOAD ? __builtin_nontemporal_load(src + q * N + idx) : src[q * N + idx];
 #pragma unroll

@@ -372,7 +372,7 @@ def test_copy_probe_refuses_bad_arguments_before_any_launch():
     assert lib.pflbm_hbm_copy(src, dst, 0, L.COPY_FORMS["w4"], None) == err
     assert lib.pflbm_hbm_copy(C.c_void_p((1 << 20) + 4), dst, 1024, L.COPY_FORMS["w16"], None) == err
     assert lib.pflbm_hbm_copy(src, dst, 1000, L.COPY_FORMS["w16"], None) == err
-    for form in ("soa43", "soa43_nt"):
+    for form in ("soa43", "soa43_nt", "soa43_f64", "soa43_f64_nt"):
         assert lib.pflbm_hbm_copy(src, dst, soa + 16, L.COPY_FORMS[form], None) == err
     assert lib.pflbm_hbm_copy(src, dst, 1024, max(L.COPY_FORMS.values()) + 1, None) == err
     assert lib.pflbm_hbm_copy(src, dst, 1024, -1, None) == err

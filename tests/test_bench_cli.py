@@ -81,10 +81,14 @@ def test_fp32_forms_are_set_against_the_faster_step_pattern_copy():
         "soa43_nt_fp32_step_pattern_128x512x128": {"GBps": 6000.0},
         "soa43_fp32_step_pattern_384x384x384": {"GBps": 5200.0},
         "soa43_nt_fp32_step_pattern_384x384x384": {"GBps": 5250.0},
-        "w4_2GiB": {"GBps": 6300.0}},
+        "w4_2GiB": {"GBps": 6300.0},
+        "soa43_f64_fp64_step_pattern_128x512x128": {"GBps": 5500.0},
+        "soa43_f64_nt_fp64_step_pattern_128x512x128": {"GBps": 6400.0}},
         "fp32_rising_bubble_128x512x128": {"roofline": {"achieved": 4500.0}},
         "fp32_drop_impact_384^3": {"roofline": {"achieved": 4462.5}}}
-    B.attach_copy_ceiling(forms)
+    head = {"roofline": {"achieved": 4800.0}}
+    B.attach_copy_ceiling(forms, {"fp64_rising_bubble_128x512x128": head})
+    assert head["roofline"]["vs_copy_ceiling"] == 0.75
     assert forms["fp32_rising_bubble_128x512x128"]["roofline"]["vs_copy_ceiling"] == 0.75
     assert forms["fp32_rising_bubble_128x512x128"]["roofline"]["copy_ceiling_GBps"] == 6000.0
     assert forms["fp32_drop_impact_384^3"]["roofline"]["vs_copy_ceiling"] == 0.85
