@@ -381,6 +381,24 @@ def test_out_of_place_step_between_saved_states_is_bitwise(precision, streaming)
             assert torch.equal(a[3][fluid], b[3][fluid]), ("phi_prev", n)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16s"])
+def test_waves_without_own_cells_read_their_ring_after_the_pulls_land(precision):
+    """Regression test for the pipelined FP32 step's direct-to-LDS pulls: in a
+    lattice with ny = 4k + 1 the last row of tiles has three waves whose own
+    cells all lie outside the lattice but which still form ring cells, and
+    with 40 planes in chunks of 4 every chunk starts with such a read.  The
+    step must wait for the pulls in those waves too; then the two-buffer step
+    equals the in-place step (which pulls into registers) bitwise."""
+    wl = W.random_state(70, 21, 40, periodic=(True, False, True), solid_fraction=0.02, seed=31)
+    say(f"case: outside rows, AB vs AA {precision}")
+    a, b = _sim(wl, precision, streaming="ab"), _sim(wl, precision, streaming="aa")
+    for n in (3, 4):
+        a.step(n)
+        b.step(n)
+        for x, y in zip(a.moments(), b.moments()):
+            assert torch.equal(x, y)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16s"])
 def test_both_streaming_schemes_give_identical_results(precision):
     """The two-buffer fused step and the in-place AA step do the same
