@@ -56,6 +56,27 @@ def test_drop_impact_fp16_storage_full_size_windows():
     _sampled_check(wl, "fp16s", 20, centres, 2e-3, 2e-3)
 
 
+def test_drop_impact_fp32_full_size_windows():
+    """The pipelined FP32 step on the 384^3 drop (the bench's FP32 drop form)."""
+    wl = W.config2()
+    centres = [(192, 100, 192), (192 + 30, 136, 192), (10, 0, 380), (383, 383, 0)]
+    _sampled_check(wl, "fp32", 20, centres, 2e-5, 2e-5)
+
+
+def test_drop_impact_slab_fp32_windows_across_the_periodic_z_faces():
+    """One GPU's z-slab of the drop, 384 x 384 x 48 (the bench's shard form,
+    z periodic where the slab exchange would be): windows on both z faces,
+    which wrap, and inside the slab."""
+    wl2 = W.config2()
+    z0 = 192 - 24
+    shard = W.Workload("drop_impact_shard_384x384x48", 384, 384, 48, (True, False, True), wl2.params,
+                       wl2.phi0[z0:z0 + 48].copy(), wl2.u0[:, z0:z0 + 48].copy(),
+                       wl2.pstar0[z0:z0 + 48].copy(), None, wl2.steps)
+    del wl2
+    centres = [(192, 100, 0), (192 + 20, 136, 47), (5, 200, 24)]
+    _sampled_check(shard, "fp32", 10, centres, 2e-5, 2e-5)
+
+
 def test_taylor_bubble_tube_mask_full_size_windows():
     wl = W.config4()
     centres = [(64, 120, 64), (64 + 42, 320, 64), (64, 1023, 5 + 4), (64 + 59, 500, 64)]
