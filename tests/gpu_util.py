@@ -62,12 +62,14 @@ def window_check(sim, wl, collision, h_n, g_n, h_n1, g_n1, centres, half=6, perm
     nz, ny, nx = wl.nz, wl.ny, wl.nx
     dims = (nx, ny, nz)
     per = wl.periodic
-    prm = OP.OracleParams.from_workload(wl.params, collision)
+    qh = h_n.shape[0]      # 15, or 27 for the D3Q27 phase lattice
+    prm = OP.OracleParams.from_workload(wl.params, collision,
+                                        phase_lattice="d3q27" if qh == 27 else "d3q15")
     worst_h = worst_g = 0.0
     ncmp = 0
-    H4 = h_n.reshape(15, nz, ny, nx)
+    H4 = h_n.reshape(qh, nz, ny, nx)
     G4 = g_n.reshape(27, nz, ny, nx)
-    H41 = h_n1.reshape(15, nz, ny, nx)
+    H41 = h_n1.reshape(qh, nz, ny, nx)
     G41 = g_n1.reshape(27, nz, ny, nx)
     for cen in centres:
         idx, keep = [], []
@@ -90,7 +92,7 @@ def window_check(sim, wl, collision, h_n, g_n, h_n1, g_n1, centres, half=6, perm
         ix, iy, iz = idx
         sel = np.ix_(iz, iy, ix)
         tsel = tuple(torch.as_tensor(a, device=H4.device) for a in sel)
-        hw = H4[(slice(None),) + tsel].reshape(15, -1).double().cpu()
+        hw = H4[(slice(None),) + tsel].reshape(qh, -1).double().cpu()
         gw = G4[(slice(None),) + tsel].reshape(27, -1).double().cpu()
         if perms is not None:
             hw, gw = hw[perms[0]], gw[perms[1]]
@@ -101,7 +103,7 @@ def window_check(sim, wl, collision, h_n, g_n, h_n1, g_n1, centres, half=6, perm
         m = torch.as_tensor((kz & ky & kx).reshape(-1))
         if solid is not None:
             m &= ~torch.as_tensor(solid.reshape(-1))
-        hg = H41[(slice(None),) + tsel].reshape(15, -1).double().cpu()
+        hg = H41[(slice(None),) + tsel].reshape(qh, -1).double().cpu()
         gg = G41[(slice(None),) + tsel].reshape(27, -1).double().cpu()
         if perms is not None:
             hg, gg = hg[perms[0]], gg[perms[1]]

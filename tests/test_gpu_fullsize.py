@@ -11,17 +11,19 @@ from gpu_util import perm_to_oracle, say, window_check
 pytestmark = pytest.mark.gpu
 
 
-def _sampled_check(wl, precision, warm, centres, tol_h, tol_g, collision="mrt", streaming="ab"):
+def _sampled_check(wl, precision, warm, centres, tol_h, tol_g, collision="mrt", streaming="ab",
+                   phase="d3q15"):
     from paper_2206_11637_amd.sim import from_workload
-    say(f"case: {wl.name} {precision} {streaming} warm {warm}")
-    sim = from_workload(wl, precision=precision, collision=collision, streaming=streaming)
+    say(f"case: {wl.name} {precision} {streaming} {phase} warm {warm}")
+    sim = from_workload(wl, precision=precision, collision=collision, streaming=streaming,
+                        phase_lattice=phase)
     r0 = sim.reduce()
     sim.step(warm)
     h_n, g_n = sim.populations()
     sim.step(1)
     h_n1, g_n1 = sim.populations()
     r1 = sim.reduce()
-    perms = (torch.as_tensor(perm_to_oracle(15)), torch.as_tensor(perm_to_oracle(27)))
+    perms = (torch.as_tensor(perm_to_oracle(sim.q_h, phase)), torch.as_tensor(perm_to_oracle(27, phase)))
     eh, eg, n = window_check(sim, wl, collision, h_n, g_n, h_n1, g_n1, centres, perms=perms)
     say(f"  {precision}: window errors h={eh:.2e} g={eg:.2e} over {n} cells; "
         f"mass drift {(r1[0] - r0[0]) / r0[0]:.2e}")
@@ -54,6 +56,13 @@ def test_drop_impact_fp16_storage_full_size_windows():
     # FP16 storage rounds every stored population (relative 2^-11 of the
     # shifted value); the bound below is a few units of that on h ~ 0.2
     _sampled_check(wl, "fp16s", 20, centres, 2e-3, 2e-3)
+
+
+def test_rising_bubble_d3q27_phase_fp32_full_size_windows():
+    """The D3Q27-phase build (the bench's FP32 D3Q27 form, k_step with 27 h)."""
+    wl = W.config1()
+    centres = [(64, 64, 64), (0, 511, 127), (90, 250, 40)]
+    _sampled_check(wl, "fp32", 20, centres, 2e-5, 2e-5, phase="d3q27")
 
 
 def test_drop_impact_fp32_full_size_windows():
