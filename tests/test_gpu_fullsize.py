@@ -50,6 +50,12 @@ def test_rising_bubble_fp64_full_size_windows():
     _sampled_check(wl, "fp64", 21, centres, 1e-12, 1e-12)
 
 
+def test_rising_bubble_fp16_storage_full_size_windows():
+    wl = W.config1()
+    centres = [(64, 64 + 16, 64), (127, 0, 0), (30, 450, 100)]
+    _sampled_check(wl, "fp16s", 20, centres, 2e-3, 2e-3)
+
+
 def test_drop_impact_fp16_storage_full_size_windows():
     wl = W.config2()
     centres = [(192, 100, 192), (192 + 30, 136, 192), (10, 0, 380), (200, 383, 5)]
