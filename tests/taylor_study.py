@@ -90,6 +90,8 @@ _G = golden()
 BO, MO, RHO_RATIO, MU_RATIO = _G["Bo"], _G["Mo"], _G["density_ratio"], _G["viscosity_ratio"]
 OMEGA_H, MOBILITY, XI = _G["omega_H"], _G["mobility"], _G["xi"]
 RE_PAPER = {64: _G["Re_PFLBM_D64"], 128: _G["Re_PFLBM_D128"]}
+UNSTABLE_PAPER = {int(d) for d in (_G["PFLBM_unstable_D"] if isinstance(_G["PFLBM_unstable_D"], (list, tuple))
+                                   else [_G["PFLBM_unstable_D"]])}
 
 
 @dataclasses.dataclass(frozen=True)
@@ -388,10 +390,11 @@ def write_table(res, path, argv):
             win = f"10-{r['Re_last_window'][1]:g} (non-finite before 15)"
         else:
             re_gas, re_all, win = "diverges", "", ""
+        paper = r["re_paper"] or ("unstable" if D in UNSTABLE_PAPER else "-")
         drift = r.get("mass_drift")
         drift = f"{drift:.1e}" if isinstance(drift, float) else "-"
         rows.append(f"| {D} | {lat} | {r['precision']} | {r.get('phase_lattice', 'd3q15')} | {r['steps']} | "
-                    f"{re_gas} | {re_all} | {win} | {r['re_paper'] or '-'} | {drift} | {r['seconds']:.0f} |")
+                    f"{re_gas} | {re_all} | {win} | {paper} | {drift} | {r['seconds']:.0f} |")
     head = ("# The paper's Taylor bubble on the GPU: Reynolds number of the rise\n\n"
             "Written by `python tests/taylor_study.py " + argv + "` on one MI355X (MRT with the bulk\n"
             "rate s_bulk = 1, two buffers; Re = rho_H D U / mu_H with U the rise velocity of the centre of\n"
