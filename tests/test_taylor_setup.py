@@ -57,3 +57,24 @@ def test_reynolds_number_follows_its_definition():
     y15 = y10 + U * 5.0 * c.t_ref
     assert abs(T.reynolds(c, y10, y15) - 64 * U / c.mu_H) < 1e-9
     assert T.RE_PAPER == {64: 26.83, 128: 27.12}
+
+
+def test_results_table_marks_windows_and_the_papers_unstable_resolutions(tmp_path):
+    """The study's markdown table: the paper's window where a run reached
+    t* = 15, the shortened window of a run that turned non-finite earlier,
+    and "unstable" for the resolutions the paper reports unstable."""
+    assert T.UNSTABLE_PAPER == {16, 32}
+    res = [dict(D=16, precision="fp32", phase_lattice="d3q15", steps=62, re_paper=None,
+                mass_drift=None, seconds=0.0),
+           dict(D=64, precision="fp32", phase_lattice="d3q15", steps=28920, Re_last=26.21,
+                Re_last_all_cells=27.71, Re_last_window=(10.0, 14.0), re_paper=26.83,
+                mass_drift=None, seconds=10.0),
+           dict(D=128, precision="fp64", phase_lattice="d3q15", steps=119670, Re=26.545,
+                Re_all_cells=26.958, re_paper=27.12, mass_drift=-6.6e-12, seconds=400.0)]
+    path = tmp_path / "t.md"
+    T.write_table(res, str(path), "--D 16 64 128")
+    rows = {int(l.split("|")[1]): [c.strip() for c in l.split("|")[1:-1]]
+            for l in path.read_text().splitlines() if l.startswith("| ") and l.split("|")[1].strip().isdigit()}
+    assert rows[16][5] == "diverges" and rows[16][8] == "unstable"
+    assert rows[64][5] == "26.210" and rows[64][7].startswith("10-14") and rows[64][8] == "26.83"
+    assert rows[128][5:9] == ["26.545", "26.958", "10-15", "27.12"] and rows[128][9] == "-6.6e-12"
